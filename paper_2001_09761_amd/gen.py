@@ -1,0 +1,196 @@
+"""Seeded synthetic calorimeter events.
+
+This module only draws inputs: hit positions, layer and event ids and energies.
+It holds none of the clustering arithmetic, so both the CPU oracle (through the
+tests) and the GPU path can be fed from it without sharing any of the method.
+
+Workloads follow the paper's performance dataset (Sec. 4.2: 100 sensor layers,
+circular Gaussian clusters whose energy falls off radially, a few per cent of
+uniform noise, 1k-10k hits per layer) with the concrete sizes and parameters of
+the five benchmark configurations:
+
+* ``config1``: 1 layer, 1,000 hits in a 100x100 cm square, 50 clusters of 19
+  hits (sigma 1 cm) plus 50 noise hits.
+* ``config2``: 1 event of 100 layers x 10,000 hits in 200x200 cm, 475
+  clusters of 20 hits per layer plus 5 % noise.
+* ``config3``: linear-scaling sweep 1k..10k hits per layer, and a hard variant
+  (20 % noise, rings and crescents).
+* ``config4``: 64 events x 100 layers with U{1000..10000} hits per layer.
+* Poisson arrival times for the served form.
+
+Every array is generated in float64 and cast to float32 (positions, energies)
+or int32 (layer and event ids). Each (event, layer) draws from its own
+``SeedSequence([seed, event, layer])`` so any event can be rebuilt alone.
+"""
+from __future__ import annotations
+
+import hashlib
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+# Clustering parameters shared by the benchmark configurations (cm, energy).
+DEFAULT_PARAMS = dict(dc=2.0, rho_c=5.0, delta_c=2.0, delta_o=4.0)
+
+
+@dataclass(frozen=True)
+class LayerSpec:
+    n_hits: int
+    extent: float = 200.0  # square side in cm, origin at (0, 0)
+    noise_frac: float = 0.05
+    cluster_size: int = 20
+    sigma: float = 1.0
+    shape: str = "gauss"  # "gauss" or "hard" (rings and crescents)
+
+
+def _split_even(total: int, parts: int) -> np.ndarray:
+    base, rem = divmod(total, parts)
+    sizes = np.full(parts, base, dtype=np.int64)
+    sizes[:rem] += 1
+    return sizes
+
+
+def gen_layer(rng: np.random.Generator, spec: LayerSpec):
+    """Hits of one layer: cluster hits grouped by cluster, then the noise hits.
+
+    Returns float64 arrays x, y, e (cast by the caller)."""
+    n = int(spec.n_hits)
+    n_noise = int(round(spec.noise_frac * n))
+    n_cl_hits = n - n_noise
+    xs, ys, es = [], [], []
+    if n_cl_hits > 0:
+        n_cl = int(math.ceil(n_cl_hits / spec.cluster_size))
+        sizes = _split_even(n_cl_hits, n_cl)
+        centres = rng.uniform(0.0, spec.extent, size=(n_cl, 2))
+        owner = np.repeat(np.arange(n_cl), sizes)
+        if spec.shape == "gauss":
+            off = rng.normal(0.0, spec.sigma, size=(n_cl_hits, 2))
+            r2 = (off * off).sum(axis=1)
+            e = 10.0 * np.exp(-r2 / (2.0 * spec.sigma * spec.sigma))
+            pos = centres[owner] + off
+        elif spec.shape == "hard":
+            # Half rings, half crescents: radius U[3,8] cm, radial jitter
+            # N(0, 0.5 cm); a crescent keeps a random half circle.
+            radius = rng.uniform(3.0, 8.0, size=n_cl)
+            crescent = np.arange(n_cl) % 2 == 1
+            phase = rng.uniform(0.0, 2.0 * np.pi, size=n_cl)
+            u = rng.uniform(0.0, 1.0, size=n_cl_hits)
+            span = np.where(crescent[owner], np.pi, 2.0 * np.pi)
+            theta = phase[owner] + u * span
+            jitter = rng.normal(0.0, 0.5, size=n_cl_hits)
+            rr = radius[owner] + jitter
+            pos = centres[owner] + np.stack([rr * np.cos(theta), rr * np.sin(theta)], axis=1)
+            e = 10.0 * np.exp(-(jitter * jitter) / 2.0)
+        else:
+            raise ValueError(f"unknown cluster shape {spec.shape!r}")
+        xs.append(pos[:, 0])
+        ys.append(pos[:, 1])
+        es.append(e)
+    if n_noise > 0:
+        noise = rng.uniform(0.0, spec.extent, size=(n_noise, 2))
+        xs.append(noise[:, 0])
+        ys.append(noise[:, 1])
+        es.append(rng.uniform(0.0, 1.0, size=n_noise))
+    if not xs:
+        z = np.zeros(0)
+        return z, z, z
+    return np.concatenate(xs), np.concatenate(ys), np.concatenate(es)
+
+
+def make_event(layer_specs, seed: int = 0, event_index: int = 0, shuffle: bool = False):
+    """One event: layers in order, each layer's hits contiguous (layer-major).
+
+    ``shuffle=True`` applies a seeded random permutation to the whole event so
+    that callers exercise arbitrary hit order."""
+    xs, ys, es, ls = [], [], [], []
+    for li, spec in enumerate(layer_specs):
+        rng = np.random.default_rng(np.random.SeedSequence([seed, event_index, li]))
+        x, y, e = gen_layer(rng, spec)
+        xs.append(x)
+        ys.append(y)
+        es.append(e)
+        ls.append(np.full(x.shape[0], li, dtype=np.int64))
+    ev = dict(
+        x=np.concatenate(xs).astype(np.float32),
+        y=np.concatenate(ys).astype(np.float32),
+        energy=np.concatenate(es).astype(np.float32),
+        layer=np.concatenate(ls).astype(np.int32),
+    )
+    if shuffle:
+        rng = np.random.default_rng(np.random.SeedSequence([seed, event_index, 1 << 20]))
+        p = rng.permutation(ev["x"].shape[0])
+        ev = {k: v[p] for k, v in ev.items()}
+    return ev
+
+
+def concat_events(events):
+    """Concatenate events into one batch SoA with a non-decreasing event id."""
+    out = {k: np.concatenate([ev[k] for ev in events]) for k in ("x", "y", "energy", "layer")}
+    out["event"] = np.concatenate(
+        [np.full(ev["x"].shape[0], i, dtype=np.int32) for i, ev in enumerate(events)]
+    ).astype(np.int32)
+    out["n_events"] = len(events)
+    return out
+
+
+def event_hash(ev) -> str:
+    h = hashlib.sha256()
+    for k in ("x", "y", "energy", "layer", "event"):
+        if k in ev:
+            h.update(np.ascontiguousarray(ev[k]).tobytes())
+    return h.hexdigest()[:16]
+
+
+# --------------------------------------------------------------------------
+# The benchmark configurations.
+# --------------------------------------------------------------------------
+
+def config1(seed: int = 0, shuffle: bool = False):
+    """1 layer, 1,000 hits in [0,100]^2: 50 clusters x 19 hits + 50 noise."""
+    spec = LayerSpec(n_hits=1000, extent=100.0, noise_frac=0.05, cluster_size=19)
+    ev = make_event([spec], seed=seed, shuffle=shuffle)
+    return ev, dict(DEFAULT_PARAMS, extent=100.0, n_layers=1)
+
+
+def config2(seed: int = 1, event_index: int = 0, n_layers: int = 100, hits_per_layer: int = 10000,
+            shuffle: bool = False):
+    """1 event of 100 layers x 10,000 hits in [0,200]^2 (1M hits)."""
+    spec = LayerSpec(n_hits=hits_per_layer, extent=200.0, noise_frac=0.05, cluster_size=20)
+    ev = make_event([spec] * n_layers, seed=seed, event_index=event_index, shuffle=shuffle)
+    return ev, dict(DEFAULT_PARAMS, extent=200.0, n_layers=n_layers)
+
+
+def config3_sweep(step: int, seed: int = 3, n_layers: int = 100):
+    """Sweep point ``step`` in 1..10: 100 layers x (1000*step) hits."""
+    spec = LayerSpec(n_hits=1000 * step, extent=200.0, noise_frac=0.05, cluster_size=20)
+    ev = make_event([spec] * n_layers, seed=seed, event_index=step)
+    return ev, dict(DEFAULT_PARAMS, extent=200.0, n_layers=n_layers)
+
+
+def config3_hard(dc: float, seed: int = 4, n_layers: int = 100, hits_per_layer: int = 10000):
+    """Hard variant: 20 % noise, rings and crescents, dc in {1, 2, 3} cm."""
+    spec = LayerSpec(n_hits=hits_per_layer, extent=200.0, noise_frac=0.20, cluster_size=20, shape="hard")
+    ev = make_event([spec] * n_layers, seed=seed, event_index=0)
+    return ev, dict(DEFAULT_PARAMS, dc=float(dc), extent=200.0, n_layers=n_layers)
+
+
+def config4_event(e: int, seed: int = 5, n_layers: int = 100, lo: int = 1000, hi: int = 10000):
+    """Event ``e`` of the batched workload: U{lo..hi} hits on each of 100 layers."""
+    specs = []
+    for li in range(n_layers):
+        rng = np.random.default_rng(np.random.SeedSequence([seed, e, li, 7]))
+        specs.append(LayerSpec(n_hits=int(rng.integers(lo, hi + 1)), extent=200.0))
+    return make_event(specs, seed=seed, event_index=e)
+
+
+def config4(n_events: int = 64, seed: int = 5, n_layers: int = 100):
+    """64 events x 100 layers x U{1000..10000} hits (about 35M hits)."""
+    evs = [config4_event(e, seed=seed, n_layers=n_layers) for e in range(n_events)]
+    return concat_events(evs), dict(DEFAULT_PARAMS, extent=200.0, n_layers=n_layers)
+
+
+def poisson_arrivals(rate_hz: float, n: int, seed: int = 6) -> np.ndarray:
+    """Arrival times (s) of a Poisson stream of ``n`` events at ``rate_hz``."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed, int(rate_hz * 1000)]))
+    return np.cumsum(rng.exponential(1.0 / rate_hz, size=n))

@@ -1,0 +1,125 @@
+"""Oracle pins: invariants (P5), the FP64 error bound (P7) and the delta_o
+monotonicity of noise rejection (P8) on generated workloads."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle_cases import adversarial_event
+from paper_2001_09761_amd import gen
+
+
+def _d2(x, y, i, j):
+    dx = (x[i] - x[j]).astype(np.float32)
+    dy = (y[i] - y[j]).astype(np.float32)
+    return (dx * dx).astype(np.float32) + (dy * dy).astype(np.float32)
+
+
+def check_invariants(ev, o, p):
+    x, y, lay = ev["x"], ev["y"], ev["layer"]
+    rho, nh, d2, cid, seed = o["rho"], o["nh"], o["delta2"], o["cluster_id"], o["is_seed"].astype(bool)
+    n = rho.size
+    dm = max(p["delta_o"], p["delta_c"])
+    dm2 = np.float32(dm) * np.float32(dm)
+    idx = np.arange(n)
+    has = nh >= 0
+    # nearest-higher is strictly higher in (rho, index), on the same layer, within d_m
+    j = nh[has]
+    i = idx[has]
+    assert np.all((rho[j] > rho[i]) | ((rho[j] == rho[i]) & (j > i)))
+    assert np.all(lay[j] == lay[i])
+    assert np.all(_d2(x, y, i, j) == d2[has]) and np.all(d2[has] < dm2)
+    assert np.all(np.isinf(d2[~has]))
+    # minimality: no higher hit within d_m is strictly closer (or equally close
+    # with a smaller index), checked against every hit of the layer
+    for l in np.unique(lay):
+        m = np.nonzero(lay == l)[0]
+        if m.size > 1500:
+            m = m[:1500]  # bounded cost; the sampled hits still see their full layer below
+        full = np.nonzero(lay == l)[0]
+        for a in m[:: max(1, m.size // 300)]:
+            dd = _d2(x, y, np.full(full.size, a), full)
+            hi = (rho[full] > rho[a]) | ((rho[full] == rho[a]) & (full > a))
+            ok = hi & (dd < dm2)
+            if not ok.any():
+                assert nh[a] == -1
+            else:
+                k = np.lexsort((full[ok], dd[ok]))[0]
+                assert nh[a] == full[ok][k] and d2[a] == dd[ok][k]
+    # decision and labels
+    k = int(seed.sum())
+    assert o["n_clusters"][0] == k
+    assert np.array_equal(cid[seed], np.arange(k, dtype=np.int32))  # seeds numbered by index
+    assert cid.min() >= -1 and cid.max() < k
+    # label >= 0 iff the root reached by following nearest-highers of
+    # registered followers is a seed
+    outl = (rho < np.float32(p["rho_c"])) & (d2 > np.float32(p["delta_o"]) ** 2)
+    follower = ~seed & ~outl & has
+    root = idx.copy()
+    for _ in range(n):
+        nxt = np.where(follower[root], nh[root], root)
+        if np.array_equal(nxt, root):
+            break
+        root = nxt
+    assert np.array_equal(cid >= 0, seed[root])
+    assert np.all(cid[outl] == -1)
+
+
+def test_invariants_config1():
+    ev, p = gen.config1()
+    o = oracle.run_event(ev, p)
+    check_invariants(ev, o, p)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_invariants_adversarial(seed):
+    ev = adversarial_event(500 + seed, n=400, n_layers=1)
+    p = dict(dc=2.0, rho_c=5.0, delta_c=2.0, delta_o=4.0)
+    o = oracle.run(ev["x"], ev["y"], ev["layer"], ev["energy"], bounds=(0, 0, 20, 20), n_layers=1, **p)
+    check_invariants(ev, o, p)
+
+
+@pytest.mark.parametrize("dc", [1.0, 2.0, 3.0])
+def test_invariants_hard_variant_small(dc):
+    ev, p = gen.config3_hard(dc, n_layers=1, hits_per_layer=2000)
+    o = oracle.run_event(ev, p)
+    check_invariants(ev, o, p)
+
+
+@pytest.mark.parametrize("which", ["config1", "config2_small", "hard_dc3"])
+def test_fp64_error(which):
+    if which == "config1":
+        ev, p = gen.config1()
+    elif which == "config2_small":
+        ev, p = gen.config2(n_layers=5)
+    else:
+        ev, p = gen.config3_hard(3.0, n_layers=3)
+    o = oracle.run_event(ev, p)
+    # Sequential float32 summation of m non-negative terms has relative error
+    # at most gamma_{m-1} = (m-1)u / (1-(m-1)u), u = 2^-24 (Higham, Accuracy
+    # and Stability of Numerical Algorithms, Sec. 4.2); the double reference
+    # adds at most one more unit of rounding.
+    rel = np.abs(o["rho"].astype(np.float64) - o["rho64"]) / np.maximum(np.abs(o["rho64"]), 1e-30)
+    # neighbourhood size m per hit from unit weights
+    ones = oracle.run(ev["x"], ev["y"], ev["layer"], np.ones_like(ev["energy"]), dc=p["dc"], rho_c=1,
+                      delta_c=p["delta_c"], delta_o=p["delta_o"], extent=p["extent"],
+                      n_layers=p["n_layers"], want=("rho",))
+    m = ones["rho"].astype(np.float64)
+    u = 2.0 ** -24
+    gamma = (m - 1) * u / (1 - (m - 1) * u)
+    assert np.all(rel <= gamma + u), float(np.max(rel - gamma))
+    if which != "hard_dc3":
+        assert rel.max() <= 1e-6
+
+
+def test_delta_o_monotone_noise():
+    """P8: for delta_o1 < delta_o2 <= delta_c, d_m = delta_c is fixed, so the
+    outliers and the noise set can only shrink as delta_o grows (Fig. 4)."""
+    ev, p = gen.config1()
+    prev_noise = None
+    for do in (0.5, 1.0, 1.5, 2.0):
+        o = oracle.run(ev["x"], ev["y"], ev["layer"], ev["energy"], dc=p["dc"], rho_c=p["rho_c"],
+                       delta_c=2.0, delta_o=do, extent=p["extent"], n_layers=1)
+        noise = o["cluster_id"] < 0
+        if prev_noise is not None:
+            assert np.all(noise <= prev_noise)
+        prev_noise = noise
