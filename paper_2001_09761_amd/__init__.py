@@ -1,0 +1,195 @@
+"""CLUE per-layer clustering on AMD Instinct MI355X (gfx950).
+
+``Context`` wraps one libclue context: ``run`` clusters one event with
+per-stage launches (plain form), ``run_batch`` clusters many events with
+persistent kernels replayed from a HIP graph (batched form). Inputs and
+outputs are torch tensors on the GPU; work is enqueued on the current torch
+stream. The serving loop lives in ``paper_2001_09761_amd.serve``.
+"""
+from __future__ import annotations
+
+import ctypes
+
+from . import _lib
+from ._lib import (ClueError, KEEP_INTERMEDIATES, NO_FOLLOWERS, TIE_PAPER_STRICT, VALIDATE,  # noqa: F401
+                   make_params)
+
+__all__ = ["Context", "ClueError", "VALIDATE", "KEEP_INTERMEDIATES", "TIE_PAPER_STRICT", "NO_FOLLOWERS",
+           "footprint_bytes"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _bounds(extent=None, bounds=None):
+    if bounds is not None:
+        return tuple(float(b) for b in bounds)
+    s = 200.0 if extent is None else float(extent)
+    return (0.0, 0.0, s, s)
+
+
+def footprint_bytes(dc, rho_c, delta_c, delta_o, max_hits, max_events=1, *, extent=None, bounds=None,
+                    n_layers=100, tile_size=0.0, flags=0) -> int:
+    p = make_params(dc, rho_c, delta_c, delta_o, _bounds(extent, bounds), n_layers, tile_size, 0, flags)
+    out = ctypes.c_uint64(0)
+    _lib.check(_lib.load().clue_footprint_bytes(ctypes.byref(p), int(max_hits), int(max_events),
+                                                ctypes.byref(out)))
+    return int(out.value)
+
+
+class Context:
+    """One libclue context (scratch arena, captured graph) on one device."""
+
+    def __init__(self, dc, rho_c, delta_c, delta_o, *, max_hits, max_events=1, extent=None, bounds=None,
+                 n_layers=100, tile_size=0.0, threads_per_query=0, flags=0, device=None, hbm_budget=0):
+        torch = _torch()
+        self._L = _lib.load()
+        self.device = torch.cuda.current_device() if device is None else int(device)
+        self.params = make_params(dc, rho_c, delta_c, delta_o, _bounds(extent, bounds), n_layers, tile_size,
+                                  threads_per_query, flags)
+        self.flags = int(flags)
+        self._ctx = ctypes.c_void_p(None)
+        rc = self._L.clue_create(ctypes.byref(self._ctx), ctypes.byref(self.params), self.device, int(max_hits),
+                                 int(max_events), int(hbm_budget))
+        if rc != 0:
+            raise ClueError(rc, self._L.clue_last_error(None).decode(errors="replace"))
+        self.max_hits = int(max_hits)
+        self.max_events = int(max_events)
+        self._last_n = 0
+
+    # -- helpers ---------------------------------------------------------
+    def _check(self, rc):
+        _lib.check(rc, self._ctx)
+
+    @staticmethod
+    def _stream(stream):
+        torch = _torch()
+        s = torch.cuda.current_stream() if stream is None else stream
+        return ctypes.c_void_p(s.cuda_stream)
+
+    def _dev(self, t, dtype, name, n):
+        torch = _torch()
+        if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+            raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+        if t.dtype != dtype:
+            raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+        if not t.is_contiguous() or t.numel() < n:
+            raise ValueError(f"{name} must be contiguous with at least {n} elements")
+        return ctypes.c_void_p(t.data_ptr() if n > 0 else 0)
+
+    def _outputs(self, n, cluster_id, is_seed, device):
+        torch = _torch()
+        if cluster_id is None:
+            cluster_id = torch.empty(n, dtype=torch.int32, device=device)
+        if is_seed is None:
+            is_seed = torch.empty(n, dtype=torch.uint8, device=device)
+        return cluster_id, is_seed
+
+    # -- runs ------------------------------------------------------------
+    def run(self, x, y, layer, energy, cluster_id=None, is_seed=None, stream=None):
+        """Cluster one event (plain form). Returns (cluster_id, is_seed)."""
+        torch = _torch()
+        n = int(x.numel())
+        cluster_id, is_seed = self._outputs(n, cluster_id, is_seed, x.device)
+        self._check(self._L.clue_run(self._ctx, n, self._dev(x, torch.float32, "x", n),
+                                     self._dev(y, torch.float32, "y", n),
+                                     self._dev(layer, torch.int32, "layer", n),
+                                     self._dev(energy, torch.float32, "energy", n),
+                                     self._dev(cluster_id, torch.int32, "cluster_id", n),
+                                     self._dev(is_seed, torch.uint8, "is_seed", n), self._stream(stream)))
+        self._last_n = n
+        return cluster_id, is_seed
+
+    def run_batch(self, event, n_events, x, y, layer, energy, cluster_id=None, is_seed=None, stream=None):
+        """Cluster a batch of events (batched form). ``event`` holds
+        non-decreasing event ids in [0, n_events)."""
+        torch = _torch()
+        n = int(x.numel())
+        cluster_id, is_seed = self._outputs(n, cluster_id, is_seed, x.device)
+        self._check(self._L.clue_run_batch(self._ctx, n, int(n_events), self._dev(event, torch.int32, "event", n),
+                                           self._dev(x, torch.float32, "x", n),
+                                           self._dev(y, torch.float32, "y", n),
+                                           self._dev(layer, torch.int32, "layer", n),
+                                           self._dev(energy, torch.float32, "energy", n),
+                                           self._dev(cluster_id, torch.int32, "cluster_id", n),
+                                           self._dev(is_seed, torch.uint8, "is_seed", n), self._stream(stream)))
+        self._last_n = n
+        return cluster_id, is_seed
+
+    def intermediates(self, stream=None):
+        """rho, nh (event-local) and delta^2 of the last run (needs KEEP_INTERMEDIATES)."""
+        torch = _torch()
+        n = self._last_n
+        dev = torch.device("cuda", self.device)
+        rho = torch.empty(n, dtype=torch.float32, device=dev)
+        nh = torch.empty(n, dtype=torch.int32, device=dev)
+        d2 = torch.empty(n, dtype=torch.float32, device=dev)
+        self._check(self._L.clue_get_intermediates(self._ctx, ctypes.c_void_p(rho.data_ptr() if n else 0),
+                                                   ctypes.c_void_p(nh.data_ptr() if n else 0),
+                                                   ctypes.c_void_p(d2.data_ptr() if n else 0),
+                                                   self._stream(stream)))
+        return dict(rho=rho, nh=nh, delta2=d2)
+
+    def followers(self, stream=None):
+        """Follower lists F_i of the last run as (fstart[n+1], flist[n_followers])."""
+        torch = _torch()
+        n = self._last_n
+        dev = torch.device("cuda", self.device)
+        fstart = torch.empty(n + 1, dtype=torch.int32, device=dev)
+        flist = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+        tot = ctypes.c_int64(0)
+        self._check(self._L.clue_get_followers(self._ctx, ctypes.c_void_p(fstart.data_ptr()),
+                                               ctypes.c_void_p(flist.data_ptr()), ctypes.byref(tot),
+                                               self._stream(stream)))
+        return fstart, flist[: int(tot.value)]
+
+    def status(self, stream=None):
+        self._check(self._L.clue_status(self._ctx, self._stream(stream)))
+
+    def reserve(self, max_hits, max_events=None):
+        me = self.max_events if max_events is None else int(max_events)
+        self._check(self._L.clue_reserve(self._ctx, int(max_hits), me))
+        self.max_hits = max(self.max_hits, int(max_hits))
+        self.max_events = max(self.max_events, me)
+
+    def set_tuning(self, tile_size=0.0, threads_per_query=0, block_x=0, block_y=0, lds_cap=0):
+        self._check(self._L.clue_set_tuning(self._ctx, float(tile_size), int(threads_per_query), int(block_x),
+                                            int(block_y), int(lds_cap)))
+
+    def tuning(self):
+        t = ctypes.c_float()
+        q, bx, by, h = (ctypes.c_int32() for _ in range(4))
+        self._check(self._L.clue_get_tuning(self._ctx, ctypes.byref(t), ctypes.byref(q), ctypes.byref(bx),
+                                            ctypes.byref(by), ctypes.byref(h)))
+        return dict(tile_size=t.value, threads_per_query=q.value, block_x=bx.value, block_y=by.value,
+                    halo=h.value)
+
+    def enable_stage_timing(self, on=True):
+        self._check(self._L.clue_enable_stage_timing(self._ctx, 1 if on else 0))
+
+    def stage_times(self):
+        ms = (ctypes.c_float * 16)()
+        names = (ctypes.c_char_p * 16)()
+        k = self._L.clue_stage_times(self._ctx, ms, names, 16)
+        if k < 0:
+            self._check(k)
+        return {names[i].decode(): float(ms[i]) for i in range(k)}
+
+    def close(self):
+        if self._ctx:
+            self._L.clue_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

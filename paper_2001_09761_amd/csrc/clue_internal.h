@@ -1,0 +1,124 @@
+// Internal declarations shared by the HIP kernels and the host runtime of
+// libclue. Nothing here crosses the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace clue {
+
+constexpr int kWG = 256;            // threads per workgroup, every kernel
+constexpr int kScanItems = 16;      // elements per thread in the prefix scans
+constexpr int kScanChunk = kWG * kScanItems;
+constexpr int kMaxRegionTiles = 1024;  // staged (block + halo) tiles per workgroup
+constexpr int kMaxRegionRows = 64;
+constexpr int kDefaultLdsCap = 2048;   // staged hits per workgroup (fast path)
+
+// Counters in device memory, cleared at the start of every run.
+enum Counter {
+  C_TICKET_TILES = 0,  // chunk tickets of the tile-count scan
+  C_TICKET_SEEDS = 1,  // chunk tickets of the seed / follower scan
+  C_QUEUE_RHO = 2,     // work-queue head of the density stage
+  C_QUEUE_NH = 3,      // work-queue head of the nearest-higher stage
+  C_COUNT = 8
+};
+
+// Device error word bits (read and cleared by clue_status).
+enum ErrBits : uint32_t {
+  E_INPUT = 1u,    // non-finite coordinate/energy, bad layer or event id
+  E_WINDOW = 2u,   // a query window left the staged halo (never expected)
+};
+
+// Per-run descriptor: sizes and the caller's buffers.
+struct RunDesc {
+  int32_t n;
+  int32_t n_events;
+  const float* x;
+  const float* y;
+  const float* e;
+  const int32_t* layer;
+  const int32_t* event;  // nullptr: single event
+  int32_t* cluster_id;
+  uint8_t* is_seed;
+};
+
+// Geometry and thresholds, fixed between re-tunings.
+struct Geom {
+  float x0, y0;     // grid origin (x_min, y_min)
+  float inv_t;      // 1 / tile size, float32
+  int32_t nx, ny;   // tiles per dimension
+  int32_t tpl;      // tiles per layer = nx * ny
+  int32_t L;        // layers
+  int32_t bx, by;   // tile block (work item) shape
+  int32_t nbx, nby; // blocks per dimension
+  int32_t bpu;      // blocks per (event, layer) unit
+  int32_t halo;     // staged halo in tiles around a block
+  int32_t maxl;     // density window tiles per dimension (2 or 3)
+  int32_t tpq;      // lanes per nearest-higher query
+  int32_t lds_cap;  // staged hits per workgroup
+  float dc2;        // fl(dc*dc)
+  float dm2;        // fl(dm*dm), dm = max(delta_o, delta_c)
+  float dcs2;       // fl(delta_c*delta_c)
+  float do2;        // fl(delta_o*delta_o)
+  float rho_c;
+  float win_dc;     // dc (1 + 2^-10): density window half width before the |x| margin
+  float win_dm;     // dm (1 + 2^-10)
+  uint32_t flags;   // CLUE_* flags
+};
+
+// Arena: device scratch owned by a context.
+struct Arena {
+  int32_t* key;          // [N]   caller order: global tile id of each hit
+  int32_t* rank;         // [N]   caller order: arrival rank within its tile
+  int32_t* tile_start;   // [TT+1] tile counts, scanned in place into CSR offsets
+  float* xs;             // [N]   slot order (tile CSR)
+  float* ys;
+  float* es;
+  int32_t* hs;           // [N]   slot -> caller (batch-global) hit index
+  float* rho;            // [N]   slot order
+  int32_t* parent;       // [N]   slot order: nearest-higher slot of a follower, else itself
+  uint8_t* flags;        // [N]   slot order: F_SEED | F_OUTLIER | F_FOLLOWER
+  int32_t* seed_rank;    // [N+1] caller order: exclusive count of seeds
+  int32_t* ev_start;     // [E+1] caller-order first hit of each event
+  int32_t* fstart;       // [N+1] caller order: follower counts, scanned into CSR offsets
+  int32_t* frank;        // [N]   slot order: rank of a follower within its owner's list
+  int32_t* flist;        // [N]   follower lists (caller-global indices until finalised)
+  float* rho_out;        // [N]   caller order, with CLUE_KEEP_INTERMEDIATES
+  int32_t* nh_out;
+  float* d2_out;
+  unsigned long long* scan_status;  // [max chunks of either scan]
+  int32_t* counters;     // [C_COUNT]
+  uint32_t* err;         // [1]
+  RunDesc* desc;         // device copy of the run descriptor (graph replays)
+  int64_t cap_hits;
+  int32_t cap_events;
+  int64_t cap_tiles;     // TT capacity
+  int64_t cap_chunks;
+};
+
+enum HitFlags : uint8_t { F_SEED = 1, F_OUTLIER = 2, F_FOLLOWER = 4 };
+
+enum Stage {
+  S_CLEAR = 0, S_HIST, S_SCAN_TILES, S_SCATTER, S_RHO, S_NH, S_SCAN_SEEDS, S_LABEL, S_FOLLOW,
+  S_COUNT
+};
+extern const char* const kStageNames[S_COUNT];
+
+struct LaunchCfg {
+  bool graph_mode;   // persistent kernels reading the descriptor from device memory
+  int persist_blocks_stream;  // persistent grid of the streaming kernels
+  int persist_blocks_items;   // persistent grid of the tile-block kernels
+  int persist_blocks_scan;    // persistent grid of the scans
+};
+
+// Host-side launches (implemented in clue_kernels.hip). `d` is the run
+// descriptor by value (plain mode) and `dd` its device copy (graph mode).
+// `ev` receives a HIP event after each stage when non-null.
+hipError_t launch_pipeline(const Geom& g, const Arena& a, const RunDesc& d, const LaunchCfg& cfg,
+                           hipStream_t s, hipEvent_t* ev);
+hipError_t launch_set_desc(const RunDesc& d, RunDesc* dd, hipStream_t s);
+hipError_t launch_validate(const Geom& g, const Arena& a, const RunDesc& d, hipStream_t s);
+int occupancy_blocks_per_cu(int which, int lds_bytes);
+int lds_bytes_for(int lds_cap);
+
+}  // namespace clue

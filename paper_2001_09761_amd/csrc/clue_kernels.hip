@@ -1,0 +1,963 @@
+// HIP kernels of libclue for gfx950 (MI355X).
+//
+// Stage map (arXiv:2001.09761):
+//   k_clear            clears counters, tile counts and scan status
+//   k_hist             fixed grid, part 1: atomic per-tile histogram (Sec. 2.1)
+//   k_scan<TILES>      exclusive prefix scan of the tile counts (decoupled look-back)
+//   k_scatter          fixed grid, part 2: scatter hits into the tile CSR
+//   k_density          rho (Eq. 3, Algorithm 1) over LDS-staged tile windows,
+//                      summed in ascending hit index by a k-way merge of the
+//                      index-sorted tile lists
+//   k_nearest_higher   nh / delta (Eq. 4, Algorithm 2) fused with the seed /
+//                      outlier / follower decision (Sec. 2.2, Algorithm 3)
+//   k_scan<SEEDS>      seed numbering by prefix scan (and follower list offsets)
+//   k_label            cluster ids: each hit follows nearest-higher links of
+//                      followers to its root (pointer jumping with path
+//                      compression); registers follower-list entries
+//   k_follow_sort      sorts each follower list by hit index, event-local ids
+//
+// Every float operation that decides a result is an explicit round-to-nearest
+// intrinsic (no contraction), so results match a plain IEEE binary32
+// evaluation of the same expressions.
+#include "clue_internal.h"
+
+#include <algorithm>
+#include <climits>
+
+namespace clue {
+
+const char* const kStageNames[S_COUNT] = {"clear",   "grid_hist",      "grid_scan",
+                                          "grid_scatter", "density", "nearest_higher",
+                                          "seed_scan", "labels", "follower_lists"};
+
+// ---------------------------------------------------------------------------
+// Run descriptor: by value (plain launches) or from device memory (graph).
+// ---------------------------------------------------------------------------
+template <bool G>
+struct DescArg;
+template <>
+struct DescArg<false> {
+  RunDesc d;
+  __device__ __forceinline__ RunDesc get() const { return d; }
+};
+template <>
+struct DescArg<true> {
+  const RunDesc* p;
+  __device__ __forceinline__ RunDesc get() const { return *p; }
+};
+
+// ---------------------------------------------------------------------------
+// Geometry helpers.
+// ---------------------------------------------------------------------------
+
+// Tile coordinate of a position: floor((v - origin) / T) clamped to the grid.
+// Monotone non-decreasing in v, which is what makes the query windows below
+// supersets of the true neighbourhoods.
+__device__ __forceinline__ int tile_coord(float v, float origin, float inv_t, int n) {
+  float t = floorf(__fmul_rn(__fsub_rn(v, origin), inv_t));
+  t = fminf(fmaxf(t, 0.0f), (float)(n - 1));
+  return (int)t;
+}
+
+__device__ __forceinline__ float dist2(float xi, float yi, float xj, float yj) {
+  float dx = __fsub_rn(xi, xj);
+  float dy = __fsub_rn(yi, yj);
+  return __fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy));
+}
+
+// Half width of a query window: the radius inflated by 2^-10 relative plus
+// 2^-20 |v|, so that rounding of v +- w can never exclude a hit whose float32
+// squared distance passes the strict threshold.
+__device__ __forceinline__ float window_half(float w, float v) {
+  return __fadd_rn(w, __fmul_rn(fabsf(v), 0x1p-20f));
+}
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+__device__ __forceinline__ int ld_relaxed(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_relaxed(int32_t* p, int v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// First caller-order hit of event e, clamped to [0, n] (memory safety for
+// unvalidated event ids).
+__device__ __forceinline__ int event_first_hit(const Arena& a, const RunDesc& d, int e) {
+  return clampi(a.ev_start[e], 0, d.n);
+}
+
+// Event that owns slot s: units are laid out event-major in the tile CSR, so
+// event e owns slots [tile_start[e*L*tpl], tile_start[(e+1)*L*tpl]).
+__device__ __forceinline__ int event_of_slot(const Geom& g, const Arena& a, const RunDesc& d, int s) {
+  if (d.n_events <= 1) return 0;
+  int lo = 0, hi = d.n_events - 1;  // largest e with start(e) <= s
+  const int64_t stride = (int64_t)g.L * g.tpl;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (a.tile_start[(int64_t)mid * stride] <= s)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// ---------------------------------------------------------------------------
+// k_clear
+// ---------------------------------------------------------------------------
+template <bool G>
+__global__ __launch_bounds__(kWG) void k_clear(DescArg<G> dg, Geom g, Arena a) {
+  const RunDesc d = dg.get();
+  const int64_t tt = (int64_t)d.n_events * g.L * g.tpl + 1;
+  const int64_t n1 = (int64_t)d.n + 1;
+  const bool fol = !(g.flags & 8u);
+  const int64_t stride = (int64_t)gridDim.x * kWG;
+  const int64_t i0 = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  for (int64_t i = i0; i < tt; i += stride) a.tile_start[i] = 0;
+  if (fol)
+    for (int64_t i = i0; i < n1; i += stride) a.fstart[i] = 0;
+  const int64_t nchunk_t = (tt + kScanChunk - 1) / kScanChunk;
+  const int64_t nchunk_s = (n1 + kScanChunk - 1) / kScanChunk;
+  for (int64_t i = i0; i < nchunk_t && i < a.cap_chunks; i += stride) a.scan_status[i] = 0ull;
+  for (int64_t i = i0; i < nchunk_s && i < a.cap_chunks; i += stride) a.scan_status[a.cap_chunks + i] = 0ull;
+  if (i0 < C_COUNT) a.counters[i0] = 0;
+  for (int64_t i = i0; i <= d.n_events; i += stride) a.ev_start[i] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// k_hist: tile of every hit, atomic count per tile, arrival rank kept.
+// ---------------------------------------------------------------------------
+template <bool G>
+__global__ __launch_bounds__(kWG) void k_hist(DescArg<G> dg, Geom g, Arena a) {
+  const RunDesc d = dg.get();
+  const int stride = gridDim.x * kWG;
+  for (int h = blockIdx.x * kWG + threadIdx.x; h < d.n; h += stride) {
+    int e = 0;
+    if (d.event) {
+      e = clampi(d.event[h], 0, d.n_events - 1);
+      const int prev = h == 0 ? -1 : clampi(d.event[h - 1], 0, d.n_events - 1);
+      for (int k = prev + 1; k <= e; ++k) a.ev_start[k] = h;
+      if (h == d.n - 1)
+        for (int k = e + 1; k <= d.n_events; ++k) a.ev_start[k] = d.n;
+    } else if (h == 0) {
+      a.ev_start[0] = 0;
+      a.ev_start[1] = d.n;
+    }
+    const int l = clampi(d.layer[h], 0, g.L - 1);
+    const int tx = tile_coord(d.x[h], g.x0, g.inv_t, g.nx);
+    const int ty = tile_coord(d.y[h], g.y0, g.inv_t, g.ny);
+    const int t = (e * g.L + l) * g.tpl + ty * g.nx + tx;
+    a.key[h] = t;
+    a.rank[h] = atomicAdd(&a.tile_start[t], 1);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_scatter: hit h goes to slot tile_start[tile] + rank (arrival order within
+// a tile; the density stage sorts each staged tile by hit index).
+// ---------------------------------------------------------------------------
+template <bool G>
+__global__ __launch_bounds__(kWG) void k_scatter(DescArg<G> dg, Geom g, Arena a) {
+  const RunDesc d = dg.get();
+  const int stride = gridDim.x * kWG;
+  for (int h = blockIdx.x * kWG + threadIdx.x; h < d.n; h += stride) {
+    const int s = a.tile_start[a.key[h]] + a.rank[h];
+    a.xs[s] = d.x[h];
+    a.ys[s] = d.y[h];
+    a.es[s] = d.e[h];
+    a.hs[s] = h;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Decoupled look-back exclusive scan, one or two channels.
+// Status word: [63:62] flag (1 aggregate, 2 inclusive prefix), [61:31]
+// channel 1, [30:0] channel 0. Every value is a count below 2^31.
+// Chunk ids come from an atomic ticket, so every chunk a workgroup waits on
+// was taken by a running workgroup that publishes without waiting: each wait
+// ends.
+// ---------------------------------------------------------------------------
+enum ScanKind { SCAN_TILES = 0, SCAN_SEEDS = 1, SCAN_SEEDS_FOLLOW = 2 };
+
+__device__ __forceinline__ unsigned long long st_pack(int flag, int v0, int v1) {
+  return ((unsigned long long)flag << 62) | ((unsigned long long)(unsigned)(v1 & 0x7fffffff) << 31) |
+         (unsigned long long)(unsigned)(v0 & 0x7fffffff);
+}
+__device__ __forceinline__ int st_flag(unsigned long long w) { return (int)(w >> 62); }
+__device__ __forceinline__ int st_v0(unsigned long long w) { return (int)(w & 0x7fffffffull); }
+__device__ __forceinline__ int st_v1(unsigned long long w) { return (int)((w >> 31) & 0x7fffffffull); }
+
+__device__ __forceinline__ int wave_incl_scan(int v, int lane) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int t = __shfl_up(v, o, 64);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+__device__ __forceinline__ int wave_sum(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <bool G, int KIND>
+__global__ __launch_bounds__(kWG) void k_scan(DescArg<G> dg, Geom g, Arena a) {
+  constexpr int NCH = KIND == SCAN_SEEDS_FOLLOW ? 2 : 1;
+  const RunDesc d = dg.get();
+  const int64_t nel = KIND == SCAN_TILES ? (int64_t)d.n_events * g.L * g.tpl : (int64_t)d.n;
+  const int64_t nout = nel + 1;  // the last output is the total
+  const int64_t nchunks = (nout + kScanChunk - 1) / kScanChunk;
+  unsigned long long* status = a.scan_status + (KIND == SCAN_TILES ? 0 : a.cap_chunks);
+  int* ticket = &a.counters[KIND == SCAN_TILES ? C_TICKET_TILES : C_TICKET_SEEDS];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  __shared__ int s_chunk;
+  __shared__ int s_wsum[NCH][kWG / 64];
+  __shared__ int s_prefix[NCH];
+
+  for (;;) {
+    if (threadIdx.x == 0) s_chunk = atomicAdd(ticket, 1);
+    __syncthreads();
+    const int64_t chunk = s_chunk;
+    __syncthreads();
+    if (chunk >= nchunks) break;
+    const int64_t base = chunk * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+
+    int v[NCH][kScanItems];
+    if constexpr (KIND == SCAN_TILES) {
+      if (base + kScanItems <= nel) {
+        const int4* p = reinterpret_cast<const int4*>(a.tile_start + base);
+#pragma unroll
+        for (int q = 0; q < kScanItems / 4; ++q) {
+          int4 w = p[q];
+          v[0][4 * q] = w.x; v[0][4 * q + 1] = w.y; v[0][4 * q + 2] = w.z; v[0][4 * q + 3] = w.w;
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) v[0][i] = base + i < nel ? a.tile_start[base + i] : 0;
+      }
+    } else {
+      const bool aligned = ((uintptr_t)d.is_seed & 15u) == 0;
+      if (aligned && base + kScanItems <= nel) {
+        uint4 w = *reinterpret_cast<const uint4*>(d.is_seed + base);
+        const unsigned ww[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) v[0][i] = (ww[i >> 2] >> (8 * (i & 3))) & 0xffu ? 1 : 0;
+      } else {
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) v[0][i] = base + i < nel ? (d.is_seed[base + i] ? 1 : 0) : 0;
+      }
+      if constexpr (NCH == 2) {
+        if (base + kScanItems <= nel) {
+          const int4* p = reinterpret_cast<const int4*>(a.fstart + base);
+#pragma unroll
+          for (int q = 0; q < kScanItems / 4; ++q) {
+            int4 w = p[q];
+            v[1][4 * q] = w.x; v[1][4 * q + 1] = w.y; v[1][4 * q + 2] = w.z; v[1][4 * q + 3] = w.w;
+          }
+        } else {
+#pragma unroll
+          for (int i = 0; i < kScanItems; ++i) v[1][i] = base + i < nel ? a.fstart[base + i] : 0;
+        }
+      }
+    }
+    // thread-local exclusive prefix
+    int tsum[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      int acc = 0;
+#pragma unroll
+      for (int i = 0; i < kScanItems; ++i) {
+        int t = v[c][i];
+        v[c][i] = acc;
+        acc += t;
+      }
+      tsum[c] = acc;
+    }
+    int texcl[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      int incl = wave_incl_scan(tsum[c], lane);
+      texcl[c] = incl - tsum[c];
+      if (lane == 63) s_wsum[c][wave] = incl;
+    }
+    __syncthreads();
+    int agg[NCH];
+    int wbase[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      int acc = 0;
+      wbase[c] = 0;
+#pragma unroll
+      for (int w = 0; w < kWG / 64; ++w) {
+        if (w == wave) wbase[c] = acc;
+        acc += s_wsum[c][w];
+      }
+      agg[c] = acc;
+    }
+    // look-back by wave 0
+    if (wave == 0) {
+      int run[NCH];
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) run[c] = 0;
+      if (chunk == 0) {
+        if (lane == 0)
+          __hip_atomic_store(&status[0], st_pack(2, agg[0], NCH == 2 ? agg[NCH - 1] : 0), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        if (lane == 0)
+          __hip_atomic_store(&status[chunk], st_pack(1, agg[0], NCH == 2 ? agg[NCH - 1] : 0), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+        int64_t look = chunk - 1;
+        for (;;) {
+          const int64_t j = look - lane;
+          unsigned long long w = j >= 0 ? __hip_atomic_load(&status[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                        : st_pack(2, 0, 0);
+          while (__any(st_flag(w) == 0)) {
+            if (st_flag(w) == 0)
+              w = __hip_atomic_load(&status[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          }
+          const unsigned long long incl_mask = __ballot(st_flag(w) == 2);
+          const int stop = incl_mask ? __ffsll((long long)incl_mask) - 1 : 64;
+          const bool take = lane <= stop;
+          run[0] += wave_sum(take ? st_v0(w) : 0);
+          if constexpr (NCH == 2) run[1] += wave_sum(take ? st_v1(w) : 0);
+          if (incl_mask) break;
+          look -= 64;
+        }
+        if (lane == 0)
+          __hip_atomic_store(&status[chunk],
+                             st_pack(2, run[0] + agg[0], NCH == 2 ? run[NCH - 1] + agg[NCH - 1] : 0),
+                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      if (lane == 0) {
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) s_prefix[c] = run[c];
+      }
+    }
+    __syncthreads();
+    // outputs
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      const int off = s_prefix[c] + wbase[c] + texcl[c];
+      int* out = KIND == SCAN_TILES ? a.tile_start : (c == 0 ? a.seed_rank : a.fstart);
+      if (base + kScanItems <= nout) {
+        int4* p = reinterpret_cast<int4*>(out + base);
+#pragma unroll
+        for (int q = 0; q < kScanItems / 4; ++q)
+          p[q] = make_int4(off + v[c][4 * q], off + v[c][4 * q + 1], off + v[c][4 * q + 2], off + v[c][4 * q + 3]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i)
+          if (base + i < nout) out[base + i] = off + v[c][i];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Tile-block work items. Item -> (event, layer) unit and a block of bx*by
+// tiles; the staged region adds `halo` tiles around the block (clamped).
+// ---------------------------------------------------------------------------
+struct Region {
+  int unit;       // event * L + layer
+  int e;          // event
+  int rx0, ry0;   // region origin (tile coordinates)
+  int rw, rh;     // region size in tiles
+  int cx0, cy0;   // core block origin relative to the region
+  int cw, ch;     // core block size
+  int total;      // hits in the region
+};
+
+// Region metadata in LDS:
+//   ts[r*(rw+1) + c]  LDS offset of region tile (r, c); c = rw is the row end
+//   row_gs[r]         global slot of the first hit of region row r
+//   row_lo[r]         LDS offset of region row r (row_lo[rh] = total)
+struct RegionLds {
+  int ts[kMaxRegionTiles + 1];
+  int row_gs[kMaxRegionRows];
+  int row_lo[kMaxRegionRows + 1];
+  int core_lo[kMaxRegionRows + 1];  // prefix of query counts over core rows
+  int item;
+};
+
+__device__ __forceinline__ void region_decode(const Geom& g, int item, Region& R) {
+  const int unit = item / g.bpu;
+  const int b = item - unit * g.bpu;
+  const int bj = b / g.nbx;
+  const int bi = b - bj * g.nbx;
+  const int tx0 = bi * g.bx, ty0 = bj * g.by;
+  const int tx1 = min(tx0 + g.bx, g.nx) - 1, ty1 = min(ty0 + g.by, g.ny) - 1;
+  R.unit = unit;
+  R.e = unit / g.L;
+  R.rx0 = max(tx0 - g.halo, 0);
+  R.ry0 = max(ty0 - g.halo, 0);
+  const int rx1 = min(tx1 + g.halo, g.nx - 1), ry1 = min(ty1 + g.halo, g.ny - 1);
+  R.rw = rx1 - R.rx0 + 1;
+  R.rh = ry1 - R.ry0 + 1;
+  R.cx0 = tx0 - R.rx0;
+  R.cy0 = ty0 - R.ry0;
+  R.cw = tx1 - tx0 + 1;
+  R.ch = ty1 - ty0 + 1;
+}
+
+// Loads the region's tile offsets and builds the LDS layout. Ends with a
+// barrier; R.total is valid in every thread afterwards.
+__device__ void region_setup(const Geom& g, const Arena& a, Region& R, RegionLds& L) {
+  const int64_t ubase = (int64_t)R.unit * g.tpl;
+  const int per_row = R.rw + 1;
+  const int ntile = R.rh * per_row;
+  for (int k = threadIdx.x; k < ntile; k += kWG) {
+    const int r = k / per_row, c = k - r * per_row;
+    L.ts[k] = a.tile_start[ubase + (int64_t)(R.ry0 + r) * g.nx + R.rx0 + c];
+  }
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    // row lengths -> LDS row offsets (rh <= 64: one wave)
+    const int r = threadIdx.x;
+    const int len = r < R.rh ? L.ts[r * per_row + R.rw] - L.ts[r * per_row] : 0;
+    const int incl = wave_incl_scan(len, r);
+    if (r < R.rh) {
+      L.row_gs[r] = L.ts[r * per_row];
+      L.row_lo[r] = incl - len;
+    }
+    if (r == 63) L.row_lo[R.rh] = incl;
+    // core query counts per core row
+    const int clen = r < R.ch ? L.ts[(R.cy0 + r) * per_row + R.cx0 + R.cw] - L.ts[(R.cy0 + r) * per_row + R.cx0] : 0;
+    const int cincl = wave_incl_scan(clen, r);
+    if (r < R.ch) L.core_lo[r] = cincl - clen;
+    if (r == 63) L.core_lo[R.ch] = cincl;
+  }
+  __syncthreads();
+  // global slot offsets -> LDS offsets
+  for (int k = threadIdx.x; k < ntile; k += kWG) {
+    const int r = k / per_row;
+    L.ts[k] = L.row_lo[r] + (L.ts[k] - L.row_gs[r]);
+  }
+  __syncthreads();
+  R.total = L.row_lo[R.rh];
+}
+
+// Region row containing LDS position p (row_lo is non-decreasing).
+__device__ __forceinline__ int region_row_of(const RegionLds& L, int rh, int p) {
+  int lo = 0, hi = rh - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (L.row_lo[mid] <= p)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// Query q of the core block -> (region row, LDS position).
+__device__ __forceinline__ void core_query(const RegionLds& L, const Region& R, int q, int& row, int& p) {
+  int cr = 0;
+  while (cr + 1 < R.ch && L.core_lo[cr + 1] <= q) ++cr;
+  row = R.cy0 + cr;
+  p = L.ts[row * (R.rw + 1) + R.cx0] + (q - L.core_lo[cr]);
+}
+
+// Pops the next work item from a queue head; uniform across the workgroup.
+__device__ __forceinline__ int pop_item(int* head, int* s_item) {
+  __syncthreads();
+  if (threadIdx.x == 0) *s_item = atomicAdd(head, 1);
+  __syncthreads();
+  return *s_item;
+}
+
+// ---------------------------------------------------------------------------
+// Density (Eq. 3): rho_i = sum of E_j over same-layer j with d2 < dc2, added
+// in ascending j. The window tiles' lists are index-sorted in LDS and merged.
+// ---------------------------------------------------------------------------
+template <int MAXL>
+__device__ __forceinline__ float density_merge(const float* __restrict__ sx, const float* __restrict__ sy,
+                                               const float* __restrict__ se, const int* __restrict__ sh,
+                                               const int* lo, const int* hi, float xi, float yi, float dc2) {
+  constexpr int K = MAXL * MAXL;
+  int cur[K], end[K], head[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    cur[k] = lo[k];
+    end[k] = hi[k];
+    head[k] = cur[k] < end[k] ? sh[cur[k]] : INT_MAX;
+  }
+  float acc = 0.0f;
+  for (;;) {
+    int m = head[0];
+#pragma unroll
+    for (int k = 1; k < K; ++k) m = min(m, head[k]);
+    if (m == INT_MAX) break;
+    int p = 0;
+#pragma unroll
+    for (int k = K - 1; k >= 0; --k)
+      if (head[k] == m) p = cur[k];
+    const float d2 = dist2(xi, yi, sx[p], sy[p]);
+    if (d2 < dc2) acc = __fadd_rn(acc, se[p]);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (head[k] == m) {
+        ++cur[k];
+        head[k] = cur[k] < end[k] ? sh[cur[k]] : INT_MAX;
+      }
+    }
+  }
+  return acc;
+}
+
+// Slow path for regions larger than the LDS budget: global tile lists in
+// arrival order; the neighbours are visited in ascending index by repeatedly
+// taking the smallest index above the previous one.
+__device__ float density_global(const Geom& g, const Arena& a, int64_t ubase, float xi, float yi) {
+  const float wx = window_half(g.win_dc, xi), wy = window_half(g.win_dc, yi);
+  const int tx0 = tile_coord(__fsub_rn(xi, wx), g.x0, g.inv_t, g.nx);
+  const int tx1 = tile_coord(__fadd_rn(xi, wx), g.x0, g.inv_t, g.nx);
+  const int ty0 = tile_coord(__fsub_rn(yi, wy), g.y0, g.inv_t, g.ny);
+  const int ty1 = tile_coord(__fadd_rn(yi, wy), g.y0, g.inv_t, g.ny);
+  float acc = 0.0f;
+  int last = -1;
+  for (;;) {
+    int best = INT_MAX;
+    float be = 0.0f;
+    for (int ty = ty0; ty <= ty1; ++ty) {
+      const int64_t t = ubase + (int64_t)ty * g.nx;
+      const int s0 = a.tile_start[t + tx0], s1 = a.tile_start[t + tx1 + 1];
+      for (int s = s0; s < s1; ++s) {
+        const int hj = a.hs[s];
+        if (hj > last && hj < best && dist2(xi, yi, a.xs[s], a.ys[s]) < g.dc2) {
+          best = hj;
+          be = a.es[s];
+        }
+      }
+    }
+    if (best == INT_MAX) break;
+    acc = __fadd_rn(acc, be);
+    last = best;
+  }
+  return acc;
+}
+
+template <bool G, int MAXL>
+__global__ __launch_bounds__(kWG) void k_density(DescArg<G> dg, Geom g, Arena a) {
+  const RunDesc d = dg.get();
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ RegionLds L;
+  __shared__ int s_item;
+  const int cap = g.lds_cap;
+  float* sx = reinterpret_cast<float*>(smem);
+  float* sy = sx + cap;
+  float* se = sy + cap;
+  int* sh = reinterpret_cast<int*>(se + cap);
+  int* stmp = sh + cap;
+  const int n_items = d.n_events * g.L * g.bpu;
+  const bool keep = g.flags & 2u;
+
+  for (;;) {
+    const int item = pop_item(&a.counters[C_QUEUE_RHO], &s_item);
+    if (item >= n_items) break;
+    Region R;
+    region_decode(g, item, R);
+    region_setup(g, a, R, L);
+    const int per_row = R.rw + 1;
+    const int nq = L.core_lo[R.ch];
+    if (nq == 0) continue;
+    const int64_t ubase = (int64_t)R.unit * g.tpl;
+    if (R.total <= cap) {
+      // stage hit indices (arrival order)
+      for (int p = threadIdx.x; p < R.total; p += kWG) {
+        const int r = region_row_of(L, R.rh, p);
+        stmp[p] = a.hs[L.row_gs[r] + (p - L.row_lo[r])];
+      }
+      __syncthreads();
+      // sort each tile by hit index: rank among tile-mates, then place
+      for (int p = threadIdx.x; p < R.total; p += kWG) {
+        int lo = 0, hi = R.rh * per_row - 1;  // last tile entry with ts <= p
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (L.ts[mid] <= p)
+            lo = mid;
+          else
+            hi = mid - 1;
+        }
+        const int t0 = L.ts[lo], t1 = L.ts[lo + 1];
+        const int hp = stmp[p];
+        int rk = 0;
+        for (int q = t0; q < t1; ++q) rk += stmp[q] < hp;
+        const int r = lo / per_row;
+        const int slot = L.row_gs[r] + (p - L.row_lo[r]);
+        const int dst = t0 + rk;
+        sx[dst] = a.xs[slot];
+        sy[dst] = a.ys[slot];
+        se[dst] = a.es[slot];
+        sh[dst] = hp;
+      }
+      __syncthreads();
+      for (int q = threadIdx.x; q < nq; q += kWG) {
+        int row, p;
+        core_query(L, R, q, row, p);
+        const int slot = L.row_gs[row] + (p - L.row_lo[row]);
+        const float xi = a.xs[slot], yi = a.ys[slot];
+        const float wx = window_half(g.win_dc, xi), wy = window_half(g.win_dc, yi);
+        const int tx0 = tile_coord(__fsub_rn(xi, wx), g.x0, g.inv_t, g.nx) - R.rx0;
+        const int tx1 = tile_coord(__fadd_rn(xi, wx), g.x0, g.inv_t, g.nx) - R.rx0;
+        const int ty0 = tile_coord(__fsub_rn(yi, wy), g.y0, g.inv_t, g.ny) - R.ry0;
+        const int ty1 = tile_coord(__fadd_rn(yi, wy), g.y0, g.inv_t, g.ny) - R.ry0;
+        int lo[MAXL * MAXL], hi[MAXL * MAXL];
+        bool ok = tx0 >= 0 && ty0 >= 0 && tx1 < R.rw && ty1 < R.rh && tx1 - tx0 < MAXL && ty1 - ty0 < MAXL;
+#pragma unroll
+        for (int jy = 0; jy < MAXL; ++jy)
+#pragma unroll
+          for (int jx = 0; jx < MAXL; ++jx) {
+            const int k = jy * MAXL + jx;
+            const int ty = ty0 + jy, tx = tx0 + jx;
+            if (ok && ty <= ty1 && tx <= tx1) {
+              lo[k] = L.ts[ty * per_row + tx];
+              hi[k] = L.ts[ty * per_row + tx + 1];
+            } else {
+              lo[k] = 0;
+              hi[k] = 0;
+            }
+          }
+        float rho;
+        if (ok) {
+          rho = density_merge<MAXL>(sx, sy, se, sh, lo, hi, xi, yi, g.dc2);
+        } else {
+          atomicOr(a.err, (uint32_t)E_WINDOW);
+          rho = density_global(g, a, ubase, xi, yi);
+        }
+        a.rho[slot] = rho;
+        if (keep) a.rho_out[a.hs[slot]] = rho;
+      }
+    } else {
+      // region does not fit in LDS: global slow path, same arithmetic
+      for (int q = threadIdx.x; q < nq; q += kWG) {
+        int row, p;
+        core_query(L, R, q, row, p);
+        const int slot = L.row_gs[row] + (p - L.row_lo[row]);
+        const float rho = density_global(g, a, ubase, a.xs[slot], a.ys[slot]);
+        a.rho[slot] = rho;
+        if (keep) a.rho_out[a.hs[slot]] = rho;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Nearest-higher (Eq. 4) and the decision (Sec. 2.2, Algorithm 3).
+// ---------------------------------------------------------------------------
+struct NhBest {
+  float d2;
+  int h;  // caller index of the nearest-higher (INT_MAX: none)
+  int p;  // its position (LDS or slot), -1: none
+};
+
+__device__ __forceinline__ void nh_consider(NhBest& b, float d2, int hq, int pq, float rq, float ri, int hi,
+                                            float dm2, bool strict) {
+  if (d2 < dm2) {
+    const bool higher = rq > ri || (!strict && rq == ri && hq > hi);
+    if (higher && (d2 < b.d2 || (d2 == b.d2 && hq < b.h))) {
+      b.d2 = d2;
+      b.h = hq;
+      b.p = pq;
+    }
+  }
+}
+
+__device__ __forceinline__ void nh_reduce(NhBest& b, int tpq) {
+  for (int o = 1; o < tpq; o <<= 1) {
+    const float od = __shfl_xor(b.d2, o, 64);
+    const int oh = __shfl_xor(b.h, o, 64);
+    const int op = __shfl_xor(b.p, o, 64);
+    if (od < b.d2 || (od == b.d2 && oh < b.h)) {
+      b.d2 = od;
+      b.h = oh;
+      b.p = op;
+    }
+  }
+}
+
+// Writes the decision for the hit in `slot` with nearest-higher `b`
+// (b.p already converted to a slot index, or -1).
+__device__ __forceinline__ void decide_and_store(const Geom& g, const Arena& a, const RunDesc& d, int slot, int hi,
+                                                 float ri, const NhBest& b, int ev_first) {
+  const bool has = b.p >= 0;
+  const float d2 = has ? b.d2 : __int_as_float(0x7f800000);
+  const bool seed = ri > g.rho_c && d2 > g.dcs2;
+  const bool outlier = ri < g.rho_c && d2 > g.do2;
+  const bool follower = !seed && !outlier && has;
+  a.parent[slot] = follower ? b.p : slot;
+  a.flags[slot] = (uint8_t)((seed ? F_SEED : 0) | (outlier ? F_OUTLIER : 0) | (follower ? F_FOLLOWER : 0));
+  d.is_seed[hi] = seed ? 1 : 0;
+  if (follower && !(g.flags & 8u)) a.frank[slot] = atomicAdd(&a.fstart[b.h], 1);
+  if (g.flags & 2u) {
+    a.nh_out[hi] = has ? b.h - ev_first : -1;
+    a.d2_out[hi] = d2;
+  }
+}
+
+template <bool G>
+__global__ __launch_bounds__(kWG) void k_nearest_higher(DescArg<G> dg, Geom g, Arena a) {
+  const RunDesc d = dg.get();
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ RegionLds L;
+  __shared__ int s_item;
+  const int cap = g.lds_cap;
+  float* sx = reinterpret_cast<float*>(smem);
+  float* sy = sx + cap;
+  float* sr = sy + cap;
+  int* sh = reinterpret_cast<int*>(sr + cap);
+  const int n_items = d.n_events * g.L * g.bpu;
+  const bool strict = g.flags & 4u;
+  const int tpq = g.tpq;
+  const int sub = threadIdx.x & (tpq - 1);
+  const int qpp = kWG / tpq;  // queries per pass
+
+  for (;;) {
+    const int item = pop_item(&a.counters[C_QUEUE_NH], &s_item);
+    if (item >= n_items) break;
+    Region R;
+    region_decode(g, item, R);
+    region_setup(g, a, R, L);
+    const int per_row = R.rw + 1;
+    const int nq = L.core_lo[R.ch];
+    if (nq == 0) continue;
+    const int64_t ubase = (int64_t)R.unit * g.tpl;
+    const int ev_first = event_first_hit(a, d, R.e);
+    const bool staged = R.total <= cap;
+    if (staged) {
+      for (int p = threadIdx.x; p < R.total; p += kWG) {
+        const int r = region_row_of(L, R.rh, p);
+        const int s = L.row_gs[r] + (p - L.row_lo[r]);
+        sx[p] = a.xs[s];
+        sy[p] = a.ys[s];
+        sr[p] = a.rho[s];
+        sh[p] = a.hs[s];
+      }
+      __syncthreads();
+    }
+    for (int base = 0; base < nq; base += qpp) {  // uniform trip count
+      const int q = base + threadIdx.x / tpq;
+      const bool active = q < nq;
+      NhBest b{__int_as_float(0x7f800000), INT_MAX, -1};
+      int slot = 0, hi = 0;
+      float ri = 0.0f;
+      if (active) {
+        int row, p;
+        core_query(L, R, q, row, p);
+        slot = L.row_gs[row] + (p - L.row_lo[row]);
+        const float xi = a.xs[slot], yi = a.ys[slot];
+        ri = a.rho[slot];
+        hi = a.hs[slot];
+        const float wx = window_half(g.win_dm, xi), wy = window_half(g.win_dm, yi);
+        const int gx0 = tile_coord(__fsub_rn(xi, wx), g.x0, g.inv_t, g.nx);
+        const int gx1 = tile_coord(__fadd_rn(xi, wx), g.x0, g.inv_t, g.nx);
+        const int gy0 = tile_coord(__fsub_rn(yi, wy), g.y0, g.inv_t, g.ny);
+        const int gy1 = tile_coord(__fadd_rn(yi, wy), g.y0, g.inv_t, g.ny);
+        const bool inside = gx0 >= R.rx0 && gy0 >= R.ry0 && gx1 < R.rx0 + R.rw && gy1 < R.ry0 + R.rh;
+        if (staged && inside) {
+          for (int ty = gy0 - R.ry0; ty <= gy1 - R.ry0; ++ty) {
+            const int q0 = L.ts[ty * per_row + gx0 - R.rx0];
+            const int q1 = L.ts[ty * per_row + gx1 - R.rx0 + 1];
+            for (int c = q0 + sub; c < q1; c += tpq)
+              nh_consider(b, dist2(xi, yi, sx[c], sy[c]), sh[c], c, sr[c], ri, hi, g.dm2, strict);
+          }
+        } else {
+          if (staged) atomicOr(a.err, (uint32_t)E_WINDOW);
+          for (int ty = gy0; ty <= gy1; ++ty) {
+            const int64_t t = ubase + (int64_t)ty * g.nx;
+            const int s0 = a.tile_start[t + gx0], s1 = a.tile_start[t + gx1 + 1];
+            for (int c = s0 + sub; c < s1; c += tpq)
+              nh_consider(b, dist2(xi, yi, a.xs[c], a.ys[c]), a.hs[c], -2 - c, a.rho[c], ri, hi, g.dm2, strict);
+          }
+        }
+      }
+      nh_reduce(b, tpq);
+      if (active && sub == 0) {
+        // position -> slot: LDS positions are >= 0, global slots are encoded as -2 - slot
+        if (b.p >= 0) {
+          const int r = region_row_of(L, R.rh, b.p);
+          b.p = L.row_gs[r] + (b.p - L.row_lo[r]);
+        } else if (b.p <= -2) {
+          b.p = -2 - b.p;
+        }
+        decide_and_store(g, a, d, slot, hi, ri, b, ev_first);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Labels: follow the follower -> nearest-higher links to the root (pointer
+// jumping with path compression; concurrent updates only ever store an
+// ancestor, so every read is an ancestor and every chase ends at the root).
+// A root that is a seed gives its seed number within the event; any other
+// root (outlier, orphan) gives -1. Also places follower-list entries.
+// ---------------------------------------------------------------------------
+template <bool G>
+__global__ __launch_bounds__(kWG) void k_label(DescArg<G> dg, Geom g, Arena a) {
+  const RunDesc d = dg.get();
+  const bool fol = !(g.flags & 8u);
+  const int stride = gridDim.x * kWG;
+  for (int s = blockIdx.x * kWG + threadIdx.x; s < d.n; s += stride) {
+    const int p0 = a.parent[s];
+    if (fol && (a.flags[s] & F_FOLLOWER)) {
+      const int owner = a.hs[p0];
+      a.flist[a.fstart[owner] + a.frank[s]] = a.hs[s];
+    }
+    int r = s, p = p0;
+    while (p != r) {
+      r = p;
+      p = ld_relaxed(&a.parent[r]);
+    }
+    if (r != s && r != p0) st_relaxed(&a.parent[s], r);
+    int lab = -1;
+    if (a.flags[r] & F_SEED) {
+      const int e = event_of_slot(g, a, d, s);
+      lab = a.seed_rank[a.hs[r]] - a.seed_rank[event_first_hit(a, d, e)];
+    }
+    d.cluster_id[a.hs[s]] = lab;
+  }
+}
+
+// Follower lists: sort each list by hit index, then make indices event-local.
+template <bool G>
+__global__ __launch_bounds__(kWG) void k_follow_sort(DescArg<G> dg, Geom g, Arena a) {
+  const RunDesc d = dg.get();
+  const int stride = gridDim.x * kWG;
+  for (int h = blockIdx.x * kWG + threadIdx.x; h < d.n; h += stride) {
+    const int b = a.fstart[h], end = a.fstart[h + 1];
+    if (b == end) continue;
+    for (int i = b + 1; i < end; ++i) {
+      const int v = a.flist[i];
+      int j = i - 1;
+      while (j >= b && a.flist[j] > v) {
+        a.flist[j + 1] = a.flist[j];
+        --j;
+      }
+      a.flist[j + 1] = v;
+    }
+    const int e = d.event ? clampi(d.event[h], 0, d.n_events - 1) : 0;
+    const int off = event_first_hit(a, d, e);
+    for (int i = b; i < end; ++i) a.flist[i] -= off;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Input validation (CLUE_VALIDATE).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kWG) void k_validate(RunDesc d, int L, uint32_t* err) {
+  const int stride = gridDim.x * kWG;
+  bool bad = false;
+  for (int h = blockIdx.x * kWG + threadIdx.x; h < d.n; h += stride) {
+    bad |= !isfinite(d.x[h]) || !isfinite(d.y[h]) || !isfinite(d.e[h]);
+    bad |= d.layer[h] < 0 || d.layer[h] >= L;
+    if (d.event) {
+      bad |= d.event[h] < 0 || d.event[h] >= d.n_events;
+      if (h > 0) bad |= d.event[h] < d.event[h - 1];
+    }
+  }
+  if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(err, (uint32_t)E_INPUT);
+}
+
+__global__ void k_set_desc(RunDesc d, RunDesc* dd) {
+  if (threadIdx.x == 0) *dd = d;
+}
+
+// ---------------------------------------------------------------------------
+// Host launches.
+// ---------------------------------------------------------------------------
+int lds_bytes_for(int lds_cap) { return lds_cap * 20; }
+
+static inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+template <bool G>
+static hipError_t launch_all(const Geom& g, const Arena& a, DescArg<G> dg, const RunDesc& host_d,
+                             const LaunchCfg& cfg, hipStream_t s, hipEvent_t* ev) {
+  // Grid sizes: plain launches are sized to the run; graph launches use
+  // persistent grids (sizes are read from the descriptor on the device).
+  const int64_t n = host_d.n;
+  const int64_t tt = (int64_t)host_d.n_events * g.L * g.tpl + 1;
+  const int64_t items = (int64_t)host_d.n_events * g.L * g.bpu;
+  auto stream_grid = [&](int64_t work) {
+    if (G) return cfg.persist_blocks_stream;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(work, kWG), 1 << 20));
+  };
+  const int g_clear = G ? cfg.persist_blocks_stream
+                        : (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(std::max(tt, n + 1), kWG), 1 << 16));
+  const int g_items = G ? cfg.persist_blocks_items : (int)std::max<int64_t>(1, items);
+  const int g_scan_t = G ? cfg.persist_blocks_scan : cdiv(tt, kScanChunk);
+  const int g_scan_s = G ? cfg.persist_blocks_scan : cdiv(n + 1, kScanChunk);
+  const bool fol = !(g.flags & 8u);
+  int k = 0;
+  auto mark = [&]() {
+    if (ev) (void)hipEventRecord(ev[k++], s);
+  };
+  mark();
+  k_clear<G><<<g_clear, kWG, 0, s>>>(dg, g, a);
+  mark();
+  k_hist<G><<<stream_grid(n), kWG, 0, s>>>(dg, g, a);
+  mark();
+  k_scan<G, SCAN_TILES><<<g_scan_t, kWG, 0, s>>>(dg, g, a);
+  mark();
+  k_scatter<G><<<stream_grid(n), kWG, 0, s>>>(dg, g, a);
+  mark();
+  const int lds = lds_bytes_for(g.lds_cap);
+  if (g.maxl == 2)
+    k_density<G, 2><<<g_items, kWG, lds, s>>>(dg, g, a);
+  else
+    k_density<G, 3><<<g_items, kWG, lds, s>>>(dg, g, a);
+  mark();
+  k_nearest_higher<G><<<g_items, kWG, g.lds_cap * 16, s>>>(dg, g, a);
+  mark();
+  if (fol)
+    k_scan<G, SCAN_SEEDS_FOLLOW><<<g_scan_s, kWG, 0, s>>>(dg, g, a);
+  else
+    k_scan<G, SCAN_SEEDS><<<g_scan_s, kWG, 0, s>>>(dg, g, a);
+  mark();
+  k_label<G><<<stream_grid(n), kWG, 0, s>>>(dg, g, a);
+  mark();
+  if (fol) k_follow_sort<G><<<stream_grid(n), kWG, 0, s>>>(dg, g, a);
+  mark();
+  return hipGetLastError();
+}
+
+hipError_t launch_pipeline(const Geom& g, const Arena& a, const RunDesc& d, const LaunchCfg& cfg, hipStream_t s,
+                           hipEvent_t* ev) {
+  if (cfg.graph_mode) {
+    DescArg<true> dg{a.desc};
+    return launch_all<true>(g, a, dg, d, cfg, s, ev);
+  }
+  DescArg<false> dg{d};
+  return launch_all<false>(g, a, dg, d, cfg, s, ev);
+}
+
+hipError_t launch_set_desc(const RunDesc& d, RunDesc* dd, hipStream_t s) {
+  k_set_desc<<<1, 64, 0, s>>>(d, dd);
+  return hipGetLastError();
+}
+
+hipError_t launch_validate(const Geom& g, const Arena& a, const RunDesc& d, hipStream_t s) {
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(d.n, kWG), 4096));
+  k_validate<<<grid, kWG, 0, s>>>(d, g.L, a.err);
+  return hipGetLastError();
+}
+
+int occupancy_blocks_per_cu(int which, int lds_bytes) {
+  int nb = 0;
+  hipError_t e = hipSuccess;
+  switch (which) {
+    case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_hist<true>, kWG, 0); break;
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_density<true, 2>, kWG, lds_bytes); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_scan<true, SCAN_SEEDS_FOLLOW>, kWG, 0); break;
+    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_nearest_higher<true>, kWG, lds_bytes); break;
+    default: break;
+  }
+  if (e != hipSuccess || nb < 1) nb = 1;
+  return nb;
+}
+
+}  // namespace clue

@@ -1,0 +1,74 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every
+function include/clue.h declares, and its host-only logic (parameter
+validation, arena sizing) behaves as documented."""
+import ctypes
+import os
+
+import pytest
+
+from paper_2001_09761_amd import _lib
+
+LIB = _lib.LIB_PATH
+
+
+def _need_lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libclue.so is not built: run __graft_entry__.build() first")
+
+
+def test_header_declares_the_boundary():
+    names = _lib.header_functions()
+    for f in ("clue_create", "clue_run", "clue_run_batch", "clue_destroy", "clue_status",
+              "clue_get_intermediates", "clue_get_followers", "clue_footprint_bytes", "clue_reserve"):
+        assert f in names
+
+
+def test_library_exports_every_declared_symbol():
+    _need_lib()
+    L = _lib.load()
+    missing = [f for f in _lib.header_functions() if not hasattr(L, f)]
+    assert not missing, missing
+
+
+def _fp(**kw):
+    L = _lib.load()
+    base = dict(dc=2.0, rho_c=5.0, delta_c=2.0, delta_o=4.0, bounds=(0, 0, 200, 200), n_layers=100)
+    base.update(kw)
+    p = _lib.make_params(base["dc"], base["rho_c"], base["delta_c"], base["delta_o"], base["bounds"],
+                         base["n_layers"], base.get("tile_size", 0.0), 0, base.get("flags", 0))
+    out = ctypes.c_uint64(0)
+    rc = L.clue_footprint_bytes(ctypes.byref(p), kw.get("max_hits", 1_000_000), kw.get("max_events", 1),
+                                ctypes.byref(out))
+    return rc, out.value
+
+
+def test_footprint_scales_linearly_and_validates():
+    _need_lib()
+    rc, b1 = _fp(max_hits=1_000_000)
+    assert rc == 0
+    rc, b2 = _fp(max_hits=2_000_000)
+    assert rc == 0 and 1.9 < b2 / b1 < 2.1
+    per_hit = (b2 - b1) / 1_000_000
+    assert 40 <= per_hit <= 80, per_hit  # documented arena cost per hit
+    rc, b3 = _fp(max_hits=1_000_000, flags=_lib.NO_FOLLOWERS)
+    assert rc == 0 and b3 < b1
+    assert _fp(dc=0.0)[0] == -1
+    assert _fp(dc=float("nan"))[0] == -1
+    assert _fp(delta_o=-1.0)[0] == -1
+    assert _fp(bounds=(0, 0, 0, 10))[0] == -1
+    assert _fp(n_layers=0)[0] == -1
+    assert _fp(tile_size=1.0)[0] == -1  # below dc: the density window would span > 3 tiles
+    assert _fp(tile_size=1e-3)[0] == -1  # grid far too fine
+    assert _fp(max_hits=-1)[0] == -1
+
+
+def test_oracle_and_product_share_nothing():
+    """The GPU library's sources never include the oracle's header, and the
+    package never imports the oracle."""
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    pkg = os.path.join(root, "paper_2001_09761_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                src = open(os.path.join(dirpath, f)).read()
+                assert "clue_oracle" not in src and "import oracle" not in src and "from oracle" not in src, f

@@ -1,0 +1,214 @@
+"""GPU parity: the HIP path (through the C ABI) against the oracle, element
+by element and bit for bit (rho, nh, delta^2, follower lists, cluster ids,
+seed flags), plain and batched forms, across tunings and edge cases."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import assert_parity, gpu_run
+from golden_cases import load_cases
+from oracle_cases import adversarial_event
+from paper_2001_09761_amd import gen
+
+pytestmark = pytest.mark.gpu
+NT = min(16, os.cpu_count() or 1)
+CASES = load_cases()
+
+
+def _ref(ev, p, **kw):
+    return oracle.run(ev["x"], ev["y"], ev["layer"], ev["energy"], dc=p["dc"], rho_c=p["rho_c"],
+                      delta_c=p["delta_c"], delta_o=p["delta_o"], extent=p.get("extent"),
+                      bounds=p.get("bounds"), n_layers=p["n_layers"], event=ev.get("event"),
+                      n_events=ev.get("n_events"), n_threads=NT, **kw)
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c["name"] for c in CASES])
+@pytest.mark.parametrize("batched", [False, True])
+def test_hand_cases(case, batched):
+    p = dict(case["params"])
+    ev = case["event"]
+    got = gpu_run(ev, p, batched=batched)
+    assert np.array_equal(got["rho"].view(np.uint32), case["rho"].view(np.uint32)), (got["rho"], case["rho"])
+    assert np.array_equal(got["nh"], case["nh"])
+    assert np.array_equal(got["cluster_id"], case["cluster_id"])
+    assert np.array_equal(got["is_seed"], case["is_seed"])
+
+
+ADV_P = dict(dc=2.0, rho_c=5.0, delta_c=2.0, delta_o=4.0, bounds=(0, 0, 20, 20), n_layers=3)
+
+
+@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("batched", [False, True])
+def test_adversarial(seed, batched):
+    ev = adversarial_event(seed, n=400 + 50 * seed, n_layers=3, unit_weights=seed % 2 == 1)
+    assert_parity(gpu_run(ev, ADV_P, batched=batched), _ref(ev, ADV_P), where=f"adv{seed}")
+
+
+TUNINGS = [
+    dict(tile_size=2.5),                      # 3x3 density lists, halo 2
+    dict(tile_size=2.1, block_x=4, block_y=4),
+    dict(tile_size=8.0, block_x=2, block_y=2),  # 2x2 lists, few tiles
+    dict(tile_size=25.0),                     # one tile covers the extent
+    dict(threads_per_query=2),
+    dict(threads_per_query=4, block_x=16, block_y=4),
+    dict(threads_per_query=8),
+    dict(lds_cap=64),                         # most regions overflow LDS: global path
+    dict(lds_cap=64, tile_size=2.5, threads_per_query=4),
+]
+
+
+@pytest.mark.parametrize("tuning", TUNINGS, ids=[str(t) for t in TUNINGS])
+@pytest.mark.parametrize("batched", [False, True])
+def test_tuning_invariance(tuning, batched):
+    ev = adversarial_event(77, n=600, n_layers=3)
+    assert_parity(gpu_run(ev, ADV_P, batched=batched, tuning=tuning), _ref(ev, ADV_P), where=str(tuning))
+
+
+def test_config1():
+    ev, p = gen.config1()
+    ref = _ref(ev, p)
+    assert_parity(gpu_run(ev, p), ref, where="cfg1 plain")
+    assert_parity(gpu_run(ev, p, batched=True), ref, where="cfg1 batched")
+    ev2, _ = gen.config1(shuffle=True)
+    assert_parity(gpu_run(ev2, p), _ref(ev2, p), where="cfg1 shuffled")
+
+
+@pytest.mark.parametrize("batched", [False, True])
+def test_config2_full(batched):
+    ev, p = gen.config2()
+    assert_parity(gpu_run(ev, p, batched=batched), _ref(ev, p), where=f"cfg2 batched={batched}")
+
+
+def test_config2_shuffled():
+    ev, p = gen.config2(n_layers=20, shuffle=True)
+    assert_parity(gpu_run(ev, p), _ref(ev, p), where="cfg2 shuffled")
+
+
+@pytest.mark.parametrize("step", [1, 4, 10])
+def test_config3_sweep(step):
+    ev, p = gen.config3_sweep(step)
+    assert_parity(gpu_run(ev, p, followers=False), _ref(ev, p, want=("rho", "nh", "delta2")),
+                  where=f"cfg3 step {step}")
+
+
+@pytest.mark.parametrize("dc", [1.0, 2.0, 3.0])
+def test_config3_hard(dc):
+    ev, p = gen.config3_hard(dc)
+    assert_parity(gpu_run(ev, p), _ref(ev, p), where=f"cfg3 hard dc={dc}")
+
+
+def test_batch_equals_events():
+    """Batched run over several events == oracle per event, indices event-local."""
+    evs = [adversarial_event(s, n=200 + 37 * s, n_layers=3) for s in range(7)]
+    evs.insert(3, {k: v[:0] for k, v in evs[0].items()})  # an empty event in the middle
+    batch = gen.concat_events(evs)
+    ref = _ref(batch, ADV_P)
+    got = gpu_run(batch, ADV_P, batched=True, n_events=batch["n_events"])
+    assert_parity(got, ref, where="batch")
+
+
+def test_config4_sample_events():
+    """Four config-4 events (U[1k,10k] hits per layer) in one batch."""
+    evs = [gen.config4_event(e) for e in range(4)]
+    batch = gen.concat_events(evs)
+    p = dict(gen.DEFAULT_PARAMS, extent=200.0, n_layers=100)
+    assert_parity(gpu_run(batch, p, batched=True, n_events=4), _ref(batch, p), where="cfg4 sample")
+
+
+def test_repeat_runs_bitwise_equal():
+    import torch
+    import paper_2001_09761_amd as clue
+    from gpu_helpers import to_dev
+    ev, p = gen.config2(n_layers=10)
+    n = ev["x"].size
+    t = to_dev(ev, torch.device("cuda", 0))
+    with clue.Context(p["dc"], p["rho_c"], p["delta_c"], p["delta_o"], max_hits=n, extent=p["extent"],
+                      n_layers=p["n_layers"]) as ctx:
+        first = [a.clone() for a in ctx.run(t["x"], t["y"], t["layer"], t["energy"])]
+        for _ in range(20):
+            cid, seed = ctx.run(t["x"], t["y"], t["layer"], t["energy"])
+            assert torch.equal(cid, first[0]) and torch.equal(seed, first[1])
+        ev_ids = torch.zeros(n, dtype=torch.int32, device=t["x"].device)
+        for _ in range(20):
+            cid, seed = ctx.run_batch(ev_ids, 1, t["x"], t["y"], t["layer"], t["energy"])
+            assert torch.equal(cid, first[0]) and torch.equal(seed, first[1])
+        ctx.status()
+
+
+def test_empty_and_single():
+    z = {k: v[:0] for k, v in adversarial_event(1, n=10).items()}
+    got = gpu_run(z, ADV_P, followers=False)
+    assert got["cluster_id"].size == 0
+    one = {k: v[:1] for k, v in adversarial_event(1, n=10).items()}
+    assert_parity(gpu_run(one, ADV_P), _ref(one, ADV_P), where="single")
+
+
+def test_dense_single_tile_and_outside_extent():
+    """Every hit in one small spot (LDS overflow path) plus hits far outside
+    the grid extent (clamped into edge tiles)."""
+    rng = np.random.default_rng(5)
+    n = 3000
+    x = rng.normal(10, 0.7, n).astype(np.float32)
+    y = rng.normal(10, 0.7, n).astype(np.float32)
+    x[:50] = rng.uniform(-100, -50, 50)
+    y[50:100] = rng.uniform(60, 90, 50)
+    ev = dict(x=x, y=y, layer=np.zeros(n, np.int32), energy=rng.uniform(0, 1, n).astype(np.float32))
+    p = dict(ADV_P, n_layers=1)
+    assert_parity(gpu_run(ev, p), _ref(ev, p), where="dense")
+
+
+def test_paper_strict_mode():
+    import paper_2001_09761_amd as clue
+    ev = adversarial_event(9, n=500, n_layers=2, unit_weights=True)
+    p = dict(ADV_P, n_layers=2)
+    got = gpu_run(ev, p, flags=clue.KEEP_INTERMEDIATES | clue.TIE_PAPER_STRICT)
+    assert_parity(got, _ref(ev, p, paper_strict=True), where="strict")
+
+
+def test_no_followers_flag():
+    import paper_2001_09761_amd as clue
+    ev = adversarial_event(10, n=500, n_layers=2)
+    p = dict(ADV_P, n_layers=2)
+    got = gpu_run(ev, p, flags=clue.KEEP_INTERMEDIATES | clue.NO_FOLLOWERS)
+    assert_parity(got, _ref(ev, p), keys=("cluster_id", "is_seed", "rho", "nh", "delta2"), where="nofollow")
+
+
+def test_validate_rejects_bad_input():
+    import torch
+    import paper_2001_09761_amd as clue
+    from gpu_helpers import to_dev
+    ev = adversarial_event(3, n=100, n_layers=1)
+    ev["x"][7] = np.nan
+    t = to_dev(ev, torch.device("cuda", 0))
+    with clue.Context(2.0, 5.0, 2.0, 4.0, max_hits=100, bounds=(0, 0, 20, 20), n_layers=1,
+                      flags=clue.VALIDATE) as ctx:
+        with pytest.raises(clue.ClueError) as ei:
+            ctx.run(t["x"], t["y"], t["layer"], t["energy"])
+        assert ei.value.code == -5
+        ev["x"][7] = 1.0
+        ev["layer"][3] = 5
+        t = to_dev(ev, torch.device("cuda", 0))
+        with pytest.raises(clue.ClueError):
+            ctx.run(t["x"], t["y"], t["layer"], t["energy"])
+
+
+def test_capacity_and_argument_errors():
+    import torch
+    import paper_2001_09761_amd as clue
+    from gpu_helpers import to_dev
+    ev = adversarial_event(3, n=100, n_layers=1)
+    t = to_dev(ev, torch.device("cuda", 0))
+    with clue.Context(2.0, 5.0, 2.0, 4.0, max_hits=50, bounds=(0, 0, 20, 20), n_layers=1) as ctx:
+        with pytest.raises(clue.ClueError) as ei:
+            ctx.run(t["x"], t["y"], t["layer"], t["energy"])
+        assert ei.value.code == -2
+        ctx.reserve(100)
+        ctx.run(t["x"], t["y"], t["layer"], t["energy"])
+        ctx.status()
+        with pytest.raises(clue.ClueError) as ei:
+            ctx.set_tuning(tile_size=1.0)  # below dc: density window would span > 3 tiles
+        assert ei.value.code == -1
+    with pytest.raises(clue.ClueError):
+        clue.Context(0.0, 5.0, 2.0, 4.0, max_hits=10, n_layers=1)
