@@ -149,19 +149,28 @@ int clue_get_followers(clue_ctx *c, int32_t *fstart, int32_t *flist, int64_t *n_
  * error (CLUE_ERR_INPUT or CLUE_ERR_DEVICE), or CLUE_OK. */
 int clue_status(clue_ctx *c, void *stream);
 
-/* Replace the tuning: tile size (cm), lanes per nearest-higher query (1, 2,
- * 4, 8), tile-block work-item shape (tiles), and hits staged in LDS per work
- * item (64..2048; larger regions take a slower global-memory path). Any
- * argument <= 0 keeps its current value. Results do not depend on the tuning.
- * Synchronous; may grow the arena. CLUE_ERR_ARG for a tile size the density
- * window cannot use (tile_size <= ~1.002 dc) or a block plus halo that is
- * too large. */
-int clue_set_tuning(clue_ctx *c, float tile_size, int32_t threads_per_query, int32_t block_x,
-                    int32_t block_y, int32_t lds_cap);
+/* Kernel tuning. Results never depend on it (every candidate the autotuner
+ * may pick gives bit-identical outputs); only speed does. */
+typedef struct {
+  float tile_size;          /* grid tile side (cm); must exceed ~1.002 dc */
+  int32_t threads_per_query; /* lanes per full-window nearest-higher query: 1, 2, 4, 8 */
+  int32_t block_x, block_y; /* tiles per work item (1..32 each) */
+  int32_t lds_cap;          /* hits staged in LDS per work item (64..2048); denser
+                               items are split per tile, then use global memory */
+  float nh_first_radius;    /* radius (cm) of the first nearest-higher pass; a hit
+                               whose nearest-higher lies strictly inside it skips
+                               the full d_m search. 0 or >= d_m: single pass */
+} clue_tuning;
 
-/* Current tuning: tile size, threads per query, tile-block shape, halo tiles. */
-int clue_get_tuning(const clue_ctx *c, float *tile_size, int32_t *threads_per_query,
-                    int32_t *block_x, int32_t *block_y, int32_t *halo);
+/* Replace the tuning. Fields <= 0 keep their current value, except
+ * nh_first_radius where only a negative value keeps it. Synchronous; may
+ * grow the arena; invalidates the captured graph. CLUE_ERR_ARG for a tile
+ * size the density window cannot use or a block plus halo that is too large
+ * (the context keeps its previous tuning). */
+int clue_set_tuning(clue_ctx *c, const clue_tuning *t);
+
+/* Current tuning, and the staged halo width in tiles it implies. */
+int clue_get_tuning(const clue_ctx *c, clue_tuning *t, int32_t *halo);
 
 /* Per-stage timing: when enabled, runs record HIP events between stages on
  * the run's stream (batched runs then launch the stage kernels directly

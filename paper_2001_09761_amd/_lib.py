@@ -31,6 +31,14 @@ class ClueParams(ctypes.Structure):
     ]
 
 
+class ClueTuning(ctypes.Structure):
+    _fields_ = [
+        ("tile_size", ctypes.c_float), ("threads_per_query", ctypes.c_int32),
+        ("block_x", ctypes.c_int32), ("block_y", ctypes.c_int32),
+        ("lds_cap", ctypes.c_int32), ("nh_first_radius", ctypes.c_float),
+    ]
+
+
 class ClueError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"{ERRORS.get(code, code)}: {msg}")
@@ -69,9 +77,8 @@ def load(path: str = LIB_PATH):
         "clue_get_intermediates": ([P, P, P, P, P], ctypes.c_int),
         "clue_get_followers": ([P, P, P, ctypes.POINTER(i64), P], ctypes.c_int),
         "clue_status": ([P, P], ctypes.c_int),
-        "clue_set_tuning": ([P, f32, i32, i32, i32, i32], ctypes.c_int),
-        "clue_get_tuning": ([P, ctypes.POINTER(f32), ctypes.POINTER(i32), ctypes.POINTER(i32),
-                             ctypes.POINTER(i32), ctypes.POINTER(i32)], ctypes.c_int),
+        "clue_set_tuning": ([P, ctypes.POINTER(ClueTuning)], ctypes.c_int),
+        "clue_get_tuning": ([P, ctypes.POINTER(ClueTuning), ctypes.POINTER(i32)], ctypes.c_int),
         "clue_enable_stage_timing": ([P, ctypes.c_int], ctypes.c_int),
         "clue_stage_times": ([P, ctypes.POINTER(f32), ctypes.POINTER(ctypes.c_char_p), ctypes.c_int], ctypes.c_int),
         "clue_last_error": ([P], ctypes.c_char_p),

@@ -22,6 +22,7 @@ struct clue_ctx {
   int n_cu = 1;
   float tile = 0.0f;
   int tpq = 1, bx = 8, by = 8, lds_cap = kDefaultLdsCap;
+  float r1 = -1.0f;  // nearest-higher first radius; negative: default d_m / 4
   LaunchCfg cfg{};
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -60,7 +61,7 @@ static inline bool finite(float v) { return std::isfinite(v); }
 // ---------------------------------------------------------------------------
 // Geometry: tile size, halo and window bounds.
 // ---------------------------------------------------------------------------
-static int plan_geom(const clue_params& p, float tile, int tpq, int bx, int by, int lds_cap, Geom& g,
+static int plan_geom(const clue_params& p, float tile, int tpq, int bx, int by, int lds_cap, float r1, Geom& g,
                      std::string& msg) {
   if (!finite(p.dc) || !(p.dc > 0.0f) || !finite(p.rho_c) || !finite(p.delta_c) || !finite(p.delta_o) ||
       p.delta_c < 0.0f || p.delta_o < 0.0f) {
@@ -84,7 +85,7 @@ static int plan_geom(const clue_params& p, float tile, int tpq, int bx, int by, 
     msg = "tile block must be within 1..32 tiles per side";
     return CLUE_ERR_ARG;
   }
-  if (lds_cap < 64 || lds_cap > 2048) {
+  if (lds_cap < 64 || lds_cap > kMaxLdsCap) {
     msg = "lds_cap must be within 64..2048 hits";
     return CLUE_ERR_ARG;
   }
@@ -118,6 +119,12 @@ static int plan_geom(const clue_params& p, float tile, int tpq, int bx, int by, 
   g.win_dc = (float)((double)p.dc * (1.0 + 1.0 / 1024.0));
   g.win_dm = (float)((double)dm * (1.0 + 1.0 / 1024.0));
   g.flags = p.flags;
+  // First nearest-higher pass: radius r1 (default d_m / 4); off when r1 <= 0
+  // or r1 >= d_m.
+  const float r1v = r1 < 0.0f ? 0.25f * dm : r1;
+  g.nh_phase1 = (r1v > 0.0f && r1v < dm && std::isfinite(r1v)) ? 1 : 0;
+  g.r1sq = g.nh_phase1 ? r1v * r1v : 0.0f;
+  g.win_r1 = g.nh_phase1 ? (float)((double)r1v * (1.0 + 1.0 / 1024.0)) : 0.0f;
   // Bound on how many tiles a query window reaches from its own tile:
   // tile_coord is floor((v - x0) * inv_t) with at most a few float32
   // roundings; the half width of a window is win + 2^-20 |v|.
@@ -315,7 +322,7 @@ int clue_footprint_bytes(const clue_params* p, int64_t max_hits, int32_t max_eve
   Geom g{};
   std::string msg;
   const int tpq = p->threads_per_query > 0 ? p->threads_per_query : 1;
-  int rc = plan_geom(*p, p->tile_size, tpq, 8, 8, kDefaultLdsCap, g, msg);
+  int rc = plan_geom(*p, p->tile_size, tpq, 8, 8, kDefaultLdsCap, -1.0f, g, msg);
   if (rc != CLUE_OK) return rc;
   ArenaPlan P;
   if (!plan_arena(g, p->flags, max_hits, max_events, P)) return CLUE_ERR_CAPACITY;
@@ -338,7 +345,7 @@ int clue_create(clue_ctx** out, const clue_params* p, int hip_device, int64_t ma
   c->tpq = p->threads_per_query > 0 ? p->threads_per_query : 1;
   c->tile = p->tile_size;
   std::string msg;
-  int rc = plan_geom(c->params, c->tile, c->tpq, c->bx, c->by, c->lds_cap, c->g, msg);
+  int rc = plan_geom(c->params, c->tile, c->tpq, c->bx, c->by, c->lds_cap, c->r1, c->g, msg);
   if (rc != CLUE_OK) {
     set_err(nullptr, rc, msg);
     delete c;
@@ -527,27 +534,22 @@ int clue_status(clue_ctx* c, void* stream) {
   return CLUE_OK;
 }
 
-int clue_set_tuning(clue_ctx* c, float tile_size, int32_t threads_per_query, int32_t block_x, int32_t block_y,
-                    int32_t lds_cap) {
-  if (!c) return CLUE_ERR_ARG;
+int clue_set_tuning(clue_ctx* c, const clue_tuning* t) {
+  if (!c || !t) return CLUE_ERR_ARG;
   Geom g{};
   std::string msg;
-  const float t = tile_size > 0.0f ? tile_size : c->tile;
-  const int tpq = threads_per_query > 0 ? threads_per_query : c->tpq;
-  const int bx = block_x > 0 ? block_x : c->bx, by = block_y > 0 ? block_y : c->by;
-  const int cap = lds_cap > 0 ? lds_cap : c->lds_cap;
-  int rc = plan_geom(c->params, t, tpq, bx, by, cap, g, msg);
+  const float tile = t->tile_size > 0.0f ? t->tile_size : c->tile;
+  const int tpq = t->threads_per_query > 0 ? t->threads_per_query : c->tpq;
+  const int bx = t->block_x > 0 ? t->block_x : c->bx, by = t->block_y > 0 ? t->block_y : c->by;
+  const int cap = t->lds_cap > 0 ? t->lds_cap : c->lds_cap;
+  const float r1 = t->nh_first_radius >= 0.0f ? t->nh_first_radius : c->r1;
+  int rc = plan_geom(c->params, tile, tpq, bx, by, cap, r1, g, msg);
   if (rc != CLUE_OK) return set_err(c, rc, msg);
   HIP_TRY(c, hipSetDevice(c->device));
   HIP_TRY(c, hipDeviceSynchronize());
   const bool regrow = (int64_t)c->a.cap_events * g.L * g.tpl + 1 > c->a.cap_tiles;
   const Geom old = c->g;
   c->g = g;
-  c->tile = t;
-  c->tpq = tpq;
-  c->bx = bx;
-  c->by = by;
-  c->lds_cap = cap;
   drop_graph(c);
   compute_cfg(c);
   if (regrow) {
@@ -558,16 +560,25 @@ int clue_set_tuning(clue_ctx* c, float tile_size, int32_t threads_per_query, int
       return rc;
     }
   }
+  c->tile = tile;
+  c->tpq = tpq;
+  c->bx = bx;
+  c->by = by;
+  c->lds_cap = cap;
+  c->r1 = r1;
   return CLUE_OK;
 }
 
-int clue_get_tuning(const clue_ctx* c, float* tile_size, int32_t* threads_per_query, int32_t* block_x,
-                    int32_t* block_y, int32_t* halo) {
+int clue_get_tuning(const clue_ctx* c, clue_tuning* t, int32_t* halo) {
   if (!c) return CLUE_ERR_ARG;
-  if (tile_size) *tile_size = (float)(1.0 / (double)c->g.inv_t);
-  if (threads_per_query) *threads_per_query = c->g.tpq;
-  if (block_x) *block_x = c->g.bx;
-  if (block_y) *block_y = c->g.by;
+  if (t) {
+    t->tile_size = (float)(1.0 / (double)c->g.inv_t);
+    t->threads_per_query = c->g.tpq;
+    t->block_x = c->g.bx;
+    t->block_y = c->g.by;
+    t->lds_cap = c->g.lds_cap;
+    t->nh_first_radius = c->g.nh_phase1 ? std::sqrt(c->g.r1sq) : 0.0f;
+  }
   if (halo) *halo = c->g.halo;
   return CLUE_OK;
 }

@@ -10,9 +10,10 @@ namespace clue {
 constexpr int kWG = 256;            // threads per workgroup, every kernel
 constexpr int kScanItems = 16;      // elements per thread in the prefix scans
 constexpr int kScanChunk = kWG * kScanItems;
-constexpr int kMaxRegionTiles = 1024;  // staged (block + halo) tiles per workgroup
+constexpr int kMaxRegionTiles = 640;   // staged region tiles, rows x (cols + 1), per workgroup
 constexpr int kMaxRegionRows = 64;
-constexpr int kDefaultLdsCap = 2048;   // staged hits per workgroup (fast path)
+constexpr int kDefaultLdsCap = 1024;   // staged hits per workgroup (fast path)
+constexpr int kMaxLdsCap = 2048;
 
 // Counters in device memory, cleared at the start of every run.
 enum Counter {
@@ -63,6 +64,9 @@ struct Geom {
   float rho_c;
   float win_dc;     // dc (1 + 2^-10): density window half width before the |x| margin
   float win_dm;     // dm (1 + 2^-10)
+  int32_t nh_phase1;  // nearest-higher first searches radius r1 < dm
+  float r1sq;       // fl(r1*r1)
+  float win_r1;     // r1 (1 + 2^-10)
   uint32_t flags;   // CLUE_* flags
 };
 

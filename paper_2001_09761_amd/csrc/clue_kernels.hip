@@ -359,16 +359,19 @@ __global__ __launch_bounds__(kWG) void k_scan(DescArg<G> dg, Geom g, Arena a) {
 }
 
 // ---------------------------------------------------------------------------
-// Tile-block work items. Item -> (event, layer) unit and a block of bx*by
-// tiles; the staged region adds `halo` tiles around the block (clamped).
+// Tile-block work items. An item is one (event, layer) unit and a block of
+// bx*by tiles (the core); its staged region adds `halo` tiles around the core
+// (clamped to the grid). Dense blocks whose region does not fit in LDS are
+// processed one core tile at a time, and a tile whose own region still does
+// not fit falls back to global memory.
 // ---------------------------------------------------------------------------
 struct Region {
   int unit;       // event * L + layer
   int e;          // event
   int rx0, ry0;   // region origin (tile coordinates)
   int rw, rh;     // region size in tiles
-  int cx0, cy0;   // core block origin relative to the region
-  int cw, ch;     // core block size
+  int cx0, cy0;   // core origin relative to the region
+  int cw, ch;     // core size in tiles
   int total;      // hits in the region
 };
 
@@ -376,21 +379,27 @@ struct Region {
 //   ts[r*(rw+1) + c]  LDS offset of region tile (r, c); c = rw is the row end
 //   row_gs[r]         global slot of the first hit of region row r
 //   row_lo[r]         LDS offset of region row r (row_lo[rh] = total)
+//   core_lo[r]        prefix of core-hit counts over core rows
 struct RegionLds {
   int ts[kMaxRegionTiles + 1];
   int row_gs[kMaxRegionRows];
   int row_lo[kMaxRegionRows + 1];
-  int core_lo[kMaxRegionRows + 1];  // prefix of query counts over core rows
-  int item;
+  int core_lo[kMaxRegionRows + 1];
 };
 
-__device__ __forceinline__ void region_decode(const Geom& g, int item, Region& R) {
-  const int unit = item / g.bpu;
+__device__ __forceinline__ void item_block(const Geom& g, int item, int& unit, int& tx0, int& ty0, int& tx1,
+                                           int& ty1) {
+  unit = item / g.bpu;
   const int b = item - unit * g.bpu;
   const int bj = b / g.nbx;
   const int bi = b - bj * g.nbx;
-  const int tx0 = bi * g.bx, ty0 = bj * g.by;
-  const int tx1 = min(tx0 + g.bx, g.nx) - 1, ty1 = min(ty0 + g.by, g.ny) - 1;
+  tx0 = bi * g.bx;
+  ty0 = bj * g.by;
+  tx1 = min(tx0 + g.bx, g.nx) - 1;
+  ty1 = min(ty0 + g.by, g.ny) - 1;
+}
+
+__device__ __forceinline__ void make_region(const Geom& g, int unit, int tx0, int ty0, int tx1, int ty1, Region& R) {
   R.unit = unit;
   R.e = unit / g.L;
   R.rx0 = max(tx0 - g.halo, 0);
@@ -404,9 +413,10 @@ __device__ __forceinline__ void region_decode(const Geom& g, int item, Region& R
   R.ch = ty1 - ty0 + 1;
 }
 
-// Loads the region's tile offsets and builds the LDS layout. Ends with a
-// barrier; R.total is valid in every thread afterwards.
+// Loads the region's tile offsets and builds the LDS layout. Starts and ends
+// with a barrier; R.total and the core counts are then valid everywhere.
 __device__ void region_setup(const Geom& g, const Arena& a, Region& R, RegionLds& L) {
+  __syncthreads();
   const int64_t ubase = (int64_t)R.unit * g.tpl;
   const int per_row = R.rw + 1;
   const int ntile = R.rh * per_row;
@@ -416,7 +426,6 @@ __device__ void region_setup(const Geom& g, const Arena& a, Region& R, RegionLds
   }
   __syncthreads();
   if (threadIdx.x < 64) {
-    // row lengths -> LDS row offsets (rh <= 64: one wave)
     const int r = threadIdx.x;
     const int len = r < R.rh ? L.ts[r * per_row + R.rw] - L.ts[r * per_row] : 0;
     const int incl = wave_incl_scan(len, r);
@@ -425,14 +434,13 @@ __device__ void region_setup(const Geom& g, const Arena& a, Region& R, RegionLds
       L.row_lo[r] = incl - len;
     }
     if (r == 63) L.row_lo[R.rh] = incl;
-    // core query counts per core row
-    const int clen = r < R.ch ? L.ts[(R.cy0 + r) * per_row + R.cx0 + R.cw] - L.ts[(R.cy0 + r) * per_row + R.cx0] : 0;
+    const int cr = (R.cy0 + r) * per_row + R.cx0;
+    const int clen = r < R.ch ? L.ts[cr + R.cw] - L.ts[cr] : 0;
     const int cincl = wave_incl_scan(clen, r);
     if (r < R.ch) L.core_lo[r] = cincl - clen;
     if (r == 63) L.core_lo[R.ch] = cincl;
   }
   __syncthreads();
-  // global slot offsets -> LDS offsets
   for (int k = threadIdx.x; k < ntile; k += kWG) {
     const int r = k / per_row;
     L.ts[k] = L.row_lo[r] + (L.ts[k] - L.row_gs[r]);
@@ -454,13 +462,15 @@ __device__ __forceinline__ int region_row_of(const RegionLds& L, int rh, int p) 
   return lo;
 }
 
-// Query q of the core block -> (region row, LDS position).
+// Core query q -> (region row, LDS position).
 __device__ __forceinline__ void core_query(const RegionLds& L, const Region& R, int q, int& row, int& p) {
   int cr = 0;
   while (cr + 1 < R.ch && L.core_lo[cr + 1] <= q) ++cr;
   row = R.cy0 + cr;
   p = L.ts[row * (R.rw + 1) + R.cx0] + (q - L.core_lo[cr]);
 }
+
+__device__ __forceinline__ int slot_of(const RegionLds& L, int row, int p) { return L.row_gs[row] + (p - L.row_lo[row]); }
 
 // Pops the next work item from a queue head; uniform across the workgroup.
 __device__ __forceinline__ int pop_item(int* head, int* s_item) {
@@ -470,21 +480,36 @@ __device__ __forceinline__ int pop_item(int* head, int* s_item) {
   return *s_item;
 }
 
+// Query window [v - w', v + w'] in tile coordinates (w' from window_half).
+struct Window {
+  int x0, x1, y0, y1;
+};
+__device__ __forceinline__ Window query_window(const Geom& g, float w, float xi, float yi) {
+  const float wx = window_half(w, xi), wy = window_half(w, yi);
+  Window W;
+  W.x0 = tile_coord(__fsub_rn(xi, wx), g.x0, g.inv_t, g.nx);
+  W.x1 = tile_coord(__fadd_rn(xi, wx), g.x0, g.inv_t, g.nx);
+  W.y0 = tile_coord(__fsub_rn(yi, wy), g.y0, g.inv_t, g.ny);
+  W.y1 = tile_coord(__fadd_rn(yi, wy), g.y0, g.inv_t, g.ny);
+  return W;
+}
+
 // ---------------------------------------------------------------------------
 // Density (Eq. 3): rho_i = sum of E_j over same-layer j with d2 < dc2, added
-// in ascending j. The window tiles' lists are index-sorted in LDS and merged.
+// in ascending j. Staged tiles are index-sorted in LDS; a query first marks
+// the passing hits of each window tile in a 64-bit mask, then merges only the
+// passing hits of the (at most MAXL x MAXL) sorted tile lists.
+// Records: (x, y, E, hit index as bits).
 // ---------------------------------------------------------------------------
 template <int MAXL>
-__device__ __forceinline__ float density_merge(const float* __restrict__ sx, const float* __restrict__ sy,
-                                               const float* __restrict__ se, const int* __restrict__ sh,
-                                               const int* lo, const int* hi, float xi, float yi, float dc2) {
+__device__ float density_merge_full(const float4* __restrict__ rec, const int* lo, const int* hi, float xi, float yi,
+                                    float dc2) {
   constexpr int K = MAXL * MAXL;
-  int cur[K], end[K], head[K];
+  int cur[K], head[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     cur[k] = lo[k];
-    end[k] = hi[k];
-    head[k] = cur[k] < end[k] ? sh[cur[k]] : INT_MAX;
+    head[k] = cur[k] < hi[k] ? __float_as_int(rec[cur[k]].w) : INT_MAX;
   }
   float acc = 0.0f;
   for (;;) {
@@ -494,38 +519,103 @@ __device__ __forceinline__ float density_merge(const float* __restrict__ sx, con
     if (m == INT_MAX) break;
     int p = 0;
 #pragma unroll
-    for (int k = K - 1; k >= 0; --k)
+    for (int k = 0; k < K; ++k)
       if (head[k] == m) p = cur[k];
-    const float d2 = dist2(xi, yi, sx[p], sy[p]);
-    if (d2 < dc2) acc = __fadd_rn(acc, se[p]);
+    const float4 r = rec[p];
+    if (dist2(xi, yi, r.x, r.y) < dc2) acc = __fadd_rn(acc, r.z);
+    const int np = p + 1;
+    int nh = INT_MAX;
+    bool more = false;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (head[k] == m) more = np < hi[k];
+    if (more) nh = __float_as_int(rec[np].w);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       if (head[k] == m) {
-        ++cur[k];
-        head[k] = cur[k] < end[k] ? sh[cur[k]] : INT_MAX;
+        cur[k] = np;
+        head[k] = nh;
       }
     }
   }
   return acc;
 }
 
-// Slow path for regions larger than the LDS budget: global tile lists in
-// arrival order; the neighbours are visited in ascending index by repeatedly
-// taking the smallest index above the previous one.
+template <int MAXL>
+__device__ __forceinline__ float density_two_pass(const float4* __restrict__ rec, const int* lo, const int* hi,
+                                                  float xi, float yi, float dc2) {
+  constexpr int K = MAXL * MAXL;
+  unsigned long long msk[K];
+  bool big = false;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    msk[k] = 0ull;
+    const int len = hi[k] - lo[k];
+    big |= len > 64;
+    const int n = min(len, 64);
+    const float4* base = rec + lo[k];
+#pragma unroll 4
+    for (int c = 0; c < n; ++c) {
+      const float2 q = *reinterpret_cast<const float2*>(base + c);
+      if (dist2(xi, yi, q.x, q.y) < dc2) msk[k] |= 1ull << c;
+    }
+  }
+  if (big) return density_merge_full<MAXL>(rec, lo, hi, xi, yi, dc2);
+  int hh[K];
+  float ee[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    hh[k] = INT_MAX;
+    ee[k] = 0.0f;
+    if (msk[k]) {
+      const float4 r = rec[lo[k] + __ffsll((long long)msk[k]) - 1];
+      hh[k] = __float_as_int(r.w);
+      ee[k] = r.z;
+    }
+  }
+  float acc = 0.0f;
+  for (;;) {
+    int m = hh[0];
+#pragma unroll
+    for (int k = 1; k < K; ++k) m = min(m, hh[k]);
+    if (m == INT_MAX) break;
+    float e = 0.0f;
+    int np = -1;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (hh[k] == m) {
+        e = ee[k];
+        msk[k] &= msk[k] - 1ull;
+        np = msk[k] ? lo[k] + __ffsll((long long)msk[k]) - 1 : -1;
+      }
+    }
+    acc = __fadd_rn(acc, e);
+    float4 r = make_float4(0.0f, 0.0f, 0.0f, __int_as_float(INT_MAX));
+    if (np >= 0) r = rec[np];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (hh[k] == m) {
+        hh[k] = __float_as_int(r.w);
+        ee[k] = r.z;
+      }
+    }
+  }
+  return acc;
+}
+
+// Global-memory density: tile lists in arrival order; the neighbours are
+// visited in ascending index by repeatedly taking the smallest index above
+// the previous one.
 __device__ float density_global(const Geom& g, const Arena& a, int64_t ubase, float xi, float yi) {
-  const float wx = window_half(g.win_dc, xi), wy = window_half(g.win_dc, yi);
-  const int tx0 = tile_coord(__fsub_rn(xi, wx), g.x0, g.inv_t, g.nx);
-  const int tx1 = tile_coord(__fadd_rn(xi, wx), g.x0, g.inv_t, g.nx);
-  const int ty0 = tile_coord(__fsub_rn(yi, wy), g.y0, g.inv_t, g.ny);
-  const int ty1 = tile_coord(__fadd_rn(yi, wy), g.y0, g.inv_t, g.ny);
+  const Window W = query_window(g, g.win_dc, xi, yi);
   float acc = 0.0f;
   int last = -1;
   for (;;) {
     int best = INT_MAX;
     float be = 0.0f;
-    for (int ty = ty0; ty <= ty1; ++ty) {
+    for (int ty = W.y0; ty <= W.y1; ++ty) {
       const int64_t t = ubase + (int64_t)ty * g.nx;
-      const int s0 = a.tile_start[t + tx0], s1 = a.tile_start[t + tx1 + 1];
+      const int s0 = a.tile_start[t + W.x0], s1 = a.tile_start[t + W.x1 + 1];
       for (int s = s0; s < s1; ++s) {
         const int hj = a.hs[s];
         if (hj > last && hj < best && dist2(xi, yi, a.xs[s], a.ys[s]) < g.dc2) {
@@ -541,118 +631,132 @@ __device__ float density_global(const Geom& g, const Arena& a, int64_t ubase, fl
   return acc;
 }
 
+template <int MAXL>
+__device__ void density_staged(const Geom& g, const Arena& a, const Region& R, const RegionLds& L, float4* rec,
+                               int* stmp, bool keep) {
+  const int per_row = R.rw + 1;
+  const int64_t ubase = (int64_t)R.unit * g.tpl;
+  for (int p = threadIdx.x; p < R.total; p += kWG) {
+    const int r = region_row_of(L, R.rh, p);
+    stmp[p] = a.hs[slot_of(L, r, p)];
+  }
+  __syncthreads();
+  // sort each tile by hit index: rank among tile-mates, then place
+  const int last_tile = R.rh * per_row - 1;
+  for (int p = threadIdx.x; p < R.total; p += kWG) {
+    int lo = 0, hi = last_tile;  // last tile entry with ts <= p
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (L.ts[mid] <= p)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    const int t0 = L.ts[lo], t1 = L.ts[lo + 1];
+    const int hp = stmp[p];
+    int rk = 0;
+    for (int q = t0; q < t1; ++q) rk += stmp[q] < hp;
+    const int slot = slot_of(L, lo / per_row, p);
+    rec[t0 + rk] = make_float4(a.xs[slot], a.ys[slot], a.es[slot], __int_as_float(hp));
+  }
+  __syncthreads();
+  const int nq = L.core_lo[R.ch];
+  for (int q = threadIdx.x; q < nq; q += kWG) {
+    int row, p;
+    core_query(L, R, q, row, p);
+    const int slot = slot_of(L, row, p);
+    const float xi = a.xs[slot], yi = a.ys[slot];
+    const Window W = query_window(g, g.win_dc, xi, yi);
+    const int tx0 = W.x0 - R.rx0, tx1 = W.x1 - R.rx0, ty0 = W.y0 - R.ry0, ty1 = W.y1 - R.ry0;
+    const bool ok = tx0 >= 0 && ty0 >= 0 && tx1 < R.rw && ty1 < R.rh && tx1 - tx0 < MAXL && ty1 - ty0 < MAXL;
+    int lo[MAXL * MAXL], hi[MAXL * MAXL];
+#pragma unroll
+    for (int jy = 0; jy < MAXL; ++jy)
+#pragma unroll
+      for (int jx = 0; jx < MAXL; ++jx) {
+        const int k = jy * MAXL + jx;
+        const int ty = ty0 + jy, tx = tx0 + jx;
+        if (ok && ty <= ty1 && tx <= tx1) {
+          lo[k] = L.ts[ty * per_row + tx];
+          hi[k] = L.ts[ty * per_row + tx + 1];
+        } else {
+          lo[k] = 0;
+          hi[k] = 0;
+        }
+      }
+    float rho;
+    if (ok) {
+      rho = density_two_pass<MAXL>(rec, lo, hi, xi, yi, g.dc2);
+    } else {
+      atomicOr(a.err, (uint32_t)E_WINDOW);
+      rho = density_global(g, a, ubase, xi, yi);
+    }
+    a.rho[slot] = rho;
+    if (keep) a.rho_out[stmp[p]] = rho;
+  }
+}
+
+__device__ void density_global_region(const Geom& g, const Arena& a, const Region& R, const RegionLds& L, bool keep) {
+  const int64_t ubase = (int64_t)R.unit * g.tpl;
+  const int nq = L.core_lo[R.ch];
+  for (int q = threadIdx.x; q < nq; q += kWG) {
+    int row, p;
+    core_query(L, R, q, row, p);
+    const int slot = slot_of(L, row, p);
+    const float rho = density_global(g, a, ubase, a.xs[slot], a.ys[slot]);
+    a.rho[slot] = rho;
+    if (keep) a.rho_out[a.hs[slot]] = rho;
+  }
+}
+
 template <bool G, int MAXL>
 __global__ __launch_bounds__(kWG) void k_density(DescArg<G> dg, Geom g, Arena a) {
   const RunDesc d = dg.get();
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ RegionLds L;
   __shared__ int s_item;
-  const int cap = g.lds_cap;
-  float* sx = reinterpret_cast<float*>(smem);
-  float* sy = sx + cap;
-  float* se = sy + cap;
-  int* sh = reinterpret_cast<int*>(se + cap);
-  int* stmp = sh + cap;
+  float4* rec = reinterpret_cast<float4*>(smem);
+  int* stmp = reinterpret_cast<int*>(rec + g.lds_cap);
   const int n_items = d.n_events * g.L * g.bpu;
   const bool keep = g.flags & 2u;
-
   for (;;) {
     const int item = pop_item(&a.counters[C_QUEUE_RHO], &s_item);
     if (item >= n_items) break;
+    int unit, tx0, ty0, tx1, ty1;
+    item_block(g, item, unit, tx0, ty0, tx1, ty1);
     Region R;
-    region_decode(g, item, R);
+    make_region(g, unit, tx0, ty0, tx1, ty1, R);
     region_setup(g, a, R, L);
-    const int per_row = R.rw + 1;
-    const int nq = L.core_lo[R.ch];
-    if (nq == 0) continue;
-    const int64_t ubase = (int64_t)R.unit * g.tpl;
-    if (R.total <= cap) {
-      // stage hit indices (arrival order)
-      for (int p = threadIdx.x; p < R.total; p += kWG) {
-        const int r = region_row_of(L, R.rh, p);
-        stmp[p] = a.hs[L.row_gs[r] + (p - L.row_lo[r])];
-      }
-      __syncthreads();
-      // sort each tile by hit index: rank among tile-mates, then place
-      for (int p = threadIdx.x; p < R.total; p += kWG) {
-        int lo = 0, hi = R.rh * per_row - 1;  // last tile entry with ts <= p
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (L.ts[mid] <= p)
-            lo = mid;
-          else
-            hi = mid - 1;
-        }
-        const int t0 = L.ts[lo], t1 = L.ts[lo + 1];
-        const int hp = stmp[p];
-        int rk = 0;
-        for (int q = t0; q < t1; ++q) rk += stmp[q] < hp;
-        const int r = lo / per_row;
-        const int slot = L.row_gs[r] + (p - L.row_lo[r]);
-        const int dst = t0 + rk;
-        sx[dst] = a.xs[slot];
-        sy[dst] = a.ys[slot];
-        se[dst] = a.es[slot];
-        sh[dst] = hp;
-      }
-      __syncthreads();
-      for (int q = threadIdx.x; q < nq; q += kWG) {
-        int row, p;
-        core_query(L, R, q, row, p);
-        const int slot = L.row_gs[row] + (p - L.row_lo[row]);
-        const float xi = a.xs[slot], yi = a.ys[slot];
-        const float wx = window_half(g.win_dc, xi), wy = window_half(g.win_dc, yi);
-        const int tx0 = tile_coord(__fsub_rn(xi, wx), g.x0, g.inv_t, g.nx) - R.rx0;
-        const int tx1 = tile_coord(__fadd_rn(xi, wx), g.x0, g.inv_t, g.nx) - R.rx0;
-        const int ty0 = tile_coord(__fsub_rn(yi, wy), g.y0, g.inv_t, g.ny) - R.ry0;
-        const int ty1 = tile_coord(__fadd_rn(yi, wy), g.y0, g.inv_t, g.ny) - R.ry0;
-        int lo[MAXL * MAXL], hi[MAXL * MAXL];
-        bool ok = tx0 >= 0 && ty0 >= 0 && tx1 < R.rw && ty1 < R.rh && tx1 - tx0 < MAXL && ty1 - ty0 < MAXL;
-#pragma unroll
-        for (int jy = 0; jy < MAXL; ++jy)
-#pragma unroll
-          for (int jx = 0; jx < MAXL; ++jx) {
-            const int k = jy * MAXL + jx;
-            const int ty = ty0 + jy, tx = tx0 + jx;
-            if (ok && ty <= ty1 && tx <= tx1) {
-              lo[k] = L.ts[ty * per_row + tx];
-              hi[k] = L.ts[ty * per_row + tx + 1];
-            } else {
-              lo[k] = 0;
-              hi[k] = 0;
-            }
-          }
-        float rho;
-        if (ok) {
-          rho = density_merge<MAXL>(sx, sy, se, sh, lo, hi, xi, yi, g.dc2);
-        } else {
-          atomicOr(a.err, (uint32_t)E_WINDOW);
-          rho = density_global(g, a, ubase, xi, yi);
-        }
-        a.rho[slot] = rho;
-        if (keep) a.rho_out[a.hs[slot]] = rho;
-      }
-    } else {
-      // region does not fit in LDS: global slow path, same arithmetic
-      for (int q = threadIdx.x; q < nq; q += kWG) {
-        int row, p;
-        core_query(L, R, q, row, p);
-        const int slot = L.row_gs[row] + (p - L.row_lo[row]);
-        const float rho = density_global(g, a, ubase, a.xs[slot], a.ys[slot]);
-        a.rho[slot] = rho;
-        if (keep) a.rho_out[a.hs[slot]] = rho;
-      }
+    if (L.core_lo[R.ch] == 0) continue;
+    if (R.total <= g.lds_cap) {
+      density_staged<MAXL>(g, a, R, L, rec, stmp, keep);
+      continue;
     }
+    for (int ty = ty0; ty <= ty1; ++ty)
+      for (int tx = tx0; tx <= tx1; ++tx) {
+        make_region(g, unit, tx, ty, tx, ty, R);
+        region_setup(g, a, R, L);
+        if (L.core_lo[R.ch] == 0) continue;
+        if (R.total <= g.lds_cap)
+          density_staged<MAXL>(g, a, R, L, rec, stmp, keep);
+        else
+          density_global_region(g, a, R, L, keep);
+      }
   }
 }
 
 // ---------------------------------------------------------------------------
 // Nearest-higher (Eq. 4) and the decision (Sec. 2.2, Algorithm 3).
+// Phase 1 searches a small window of radius r1 <= d_m; when its best
+// higher hit lies strictly within r1, no hit outside that window can be
+// closer, so the query is done. Other queries are queued in LDS and searched
+// over the full d_m window with `tpq` lanes each (phase 2).
+// Records: (x, y, rho, hit index as bits).
 // ---------------------------------------------------------------------------
 struct NhBest {
   float d2;
   int h;  // caller index of the nearest-higher (INT_MAX: none)
-  int p;  // its position (LDS or slot), -1: none
+  int p;  // its position: LDS position >= 0, global slot s encoded as -2 - s, -1 none
 };
 
 __device__ __forceinline__ void nh_consider(NhBest& b, float d2, int hq, int pq, float rq, float ri, int hi,
@@ -680,8 +784,8 @@ __device__ __forceinline__ void nh_reduce(NhBest& b, int tpq) {
   }
 }
 
-// Writes the decision for the hit in `slot` with nearest-higher `b`
-// (b.p already converted to a slot index, or -1).
+// Writes the decision for the hit in `slot` with nearest-higher `b` (b.p
+// already converted to a slot index, or -1).
 __device__ __forceinline__ void decide_and_store(const Geom& g, const Arena& a, const RunDesc& d, int slot, int hi,
                                                  float ri, const NhBest& b, int ev_first) {
   const bool has = b.p >= 0;
@@ -699,94 +803,170 @@ __device__ __forceinline__ void decide_and_store(const Geom& g, const Arena& a, 
   }
 }
 
+// Scans window tiles [tx0..tx1] x [ty0..ty1] (region coordinates) of the
+// staged records with lanes sub, sub + step, ...
+__device__ __forceinline__ void nh_scan_staged(const float4* __restrict__ rec, const RegionLds& L, int per_row,
+                                               int tx0, int tx1, int ty0, int ty1, int sub, int step, float xi,
+                                               float yi, float ri, int hi, float dm2, bool strict, NhBest& b) {
+  for (int ty = ty0; ty <= ty1; ++ty) {
+    const int q0 = L.ts[ty * per_row + tx0];
+    const int q1 = L.ts[ty * per_row + tx1 + 1];
+#pragma unroll 4
+    for (int c = q0 + sub; c < q1; c += step) {
+      const float4 r = rec[c];
+      nh_consider(b, dist2(xi, yi, r.x, r.y), __float_as_int(r.w), c, r.z, ri, hi, dm2, strict);
+    }
+  }
+}
+
+__device__ void nh_staged(const Geom& g, const Arena& a, const RunDesc& d, const Region& R, const RegionLds& L,
+                          float4* rec, int* queue, int* s_qn, int ev_first, bool strict) {
+  const int per_row = R.rw + 1;
+  const int64_t ubase = (int64_t)R.unit * g.tpl;
+  for (int p = threadIdx.x; p < R.total; p += kWG) {
+    const int s = slot_of(L, region_row_of(L, R.rh, p), p);
+    rec[p] = make_float4(a.xs[s], a.ys[s], a.rho[s], __int_as_float(a.hs[s]));
+  }
+  if (threadIdx.x == 0) *s_qn = 0;
+  __syncthreads();
+  const int nq = L.core_lo[R.ch];
+  // phase 1: radius r1
+  for (int q = threadIdx.x; q < nq; q += kWG) {
+    bool done = false;
+    if (g.nh_phase1) {
+      int row, p;
+      core_query(L, R, q, row, p);
+      const float4 me = rec[p];
+      const int hi = __float_as_int(me.w);
+      const Window W = query_window(g, g.win_r1, me.x, me.y);
+      const int tx0 = W.x0 - R.rx0, tx1 = W.x1 - R.rx0, ty0 = W.y0 - R.ry0, ty1 = W.y1 - R.ry0;
+      if (tx0 >= 0 && ty0 >= 0 && tx1 < R.rw && ty1 < R.rh) {
+        NhBest b{__int_as_float(0x7f800000), INT_MAX, -1};
+        nh_scan_staged(rec, L, per_row, tx0, tx1, ty0, ty1, 0, 1, me.x, me.y, me.z, hi, g.dm2, strict, b);
+        if (b.p >= 0 && b.d2 < g.r1sq) {
+          b.p = slot_of(L, region_row_of(L, R.rh, b.p), b.p);
+          decide_and_store(g, a, d, slot_of(L, row, p), hi, me.z, b, ev_first);
+          done = true;
+        }
+      }
+    }
+    if (!done) queue[atomicAdd(s_qn, 1)] = q;
+  }
+  __syncthreads();
+  // phase 2: full d_m window, tpq lanes per query
+  const int nu = *s_qn;
+  const int tpq = g.tpq;
+  const int sub = threadIdx.x & (tpq - 1);
+  const int qpp = kWG / tpq;
+  for (int base = 0; base < nu; base += qpp) {  // uniform trip count
+    const int qi = base + threadIdx.x / tpq;
+    const bool active = qi < nu;
+    NhBest b{__int_as_float(0x7f800000), INT_MAX, -1};
+    int slot = 0, hi = 0;
+    float ri = 0.0f;
+    if (active) {
+      int row, p;
+      core_query(L, R, queue[qi], row, p);
+      slot = slot_of(L, row, p);
+      const float4 me = rec[p];
+      ri = me.z;
+      hi = __float_as_int(me.w);
+      const Window W = query_window(g, g.win_dm, me.x, me.y);
+      const int tx0 = W.x0 - R.rx0, tx1 = W.x1 - R.rx0, ty0 = W.y0 - R.ry0, ty1 = W.y1 - R.ry0;
+      if (tx0 >= 0 && ty0 >= 0 && tx1 < R.rw && ty1 < R.rh) {
+        nh_scan_staged(rec, L, per_row, tx0, tx1, ty0, ty1, sub, tpq, me.x, me.y, ri, hi, g.dm2, strict, b);
+      } else {
+        atomicOr(a.err, (uint32_t)E_WINDOW);
+        for (int ty = W.y0; ty <= W.y1; ++ty) {
+          const int64_t t = ubase + (int64_t)ty * g.nx;
+          const int s0 = a.tile_start[t + W.x0], s1 = a.tile_start[t + W.x1 + 1];
+          for (int c = s0 + sub; c < s1; c += tpq)
+            nh_consider(b, dist2(me.x, me.y, a.xs[c], a.ys[c]), a.hs[c], -2 - c, a.rho[c], ri, hi, g.dm2, strict);
+        }
+      }
+    }
+    nh_reduce(b, tpq);
+    if (active && sub == 0) {
+      if (b.p >= 0)
+        b.p = slot_of(L, region_row_of(L, R.rh, b.p), b.p);
+      else if (b.p <= -2)
+        b.p = -2 - b.p;
+      decide_and_store(g, a, d, slot, hi, ri, b, ev_first);
+    }
+  }
+}
+
+__device__ void nh_global_region(const Geom& g, const Arena& a, const RunDesc& d, const Region& R, const RegionLds& L,
+                                 int ev_first, bool strict) {
+  const int64_t ubase = (int64_t)R.unit * g.tpl;
+  const int nq = L.core_lo[R.ch];
+  const int tpq = g.tpq;
+  const int sub = threadIdx.x & (tpq - 1);
+  const int qpp = kWG / tpq;
+  for (int base = 0; base < nq; base += qpp) {
+    const int q = base + threadIdx.x / tpq;
+    const bool active = q < nq;
+    NhBest b{__int_as_float(0x7f800000), INT_MAX, -1};
+    int slot = 0, hi = 0;
+    float ri = 0.0f;
+    if (active) {
+      int row, p;
+      core_query(L, R, q, row, p);
+      slot = slot_of(L, row, p);
+      const float xi = a.xs[slot], yi = a.ys[slot];
+      ri = a.rho[slot];
+      hi = a.hs[slot];
+      const Window W = query_window(g, g.win_dm, xi, yi);
+      for (int ty = W.y0; ty <= W.y1; ++ty) {
+        const int64_t t = ubase + (int64_t)ty * g.nx;
+        const int s0 = a.tile_start[t + W.x0], s1 = a.tile_start[t + W.x1 + 1];
+        for (int c = s0 + sub; c < s1; c += tpq)
+          nh_consider(b, dist2(xi, yi, a.xs[c], a.ys[c]), a.hs[c], -2 - c, a.rho[c], ri, hi, g.dm2, strict);
+      }
+    }
+    nh_reduce(b, tpq);
+    if (active && sub == 0) {
+      if (b.p <= -2) b.p = -2 - b.p;
+      decide_and_store(g, a, d, slot, hi, ri, b, ev_first);
+    }
+  }
+}
+
 template <bool G>
 __global__ __launch_bounds__(kWG) void k_nearest_higher(DescArg<G> dg, Geom g, Arena a) {
   const RunDesc d = dg.get();
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ RegionLds L;
   __shared__ int s_item;
-  const int cap = g.lds_cap;
-  float* sx = reinterpret_cast<float*>(smem);
-  float* sy = sx + cap;
-  float* sr = sy + cap;
-  int* sh = reinterpret_cast<int*>(sr + cap);
+  __shared__ int s_qn;
+  float4* rec = reinterpret_cast<float4*>(smem);
+  int* queue = reinterpret_cast<int*>(rec + g.lds_cap);
   const int n_items = d.n_events * g.L * g.bpu;
   const bool strict = g.flags & 4u;
-  const int tpq = g.tpq;
-  const int sub = threadIdx.x & (tpq - 1);
-  const int qpp = kWG / tpq;  // queries per pass
-
   for (;;) {
     const int item = pop_item(&a.counters[C_QUEUE_NH], &s_item);
     if (item >= n_items) break;
+    int unit, tx0, ty0, tx1, ty1;
+    item_block(g, item, unit, tx0, ty0, tx1, ty1);
     Region R;
-    region_decode(g, item, R);
+    make_region(g, unit, tx0, ty0, tx1, ty1, R);
     region_setup(g, a, R, L);
-    const int per_row = R.rw + 1;
-    const int nq = L.core_lo[R.ch];
-    if (nq == 0) continue;
-    const int64_t ubase = (int64_t)R.unit * g.tpl;
+    if (L.core_lo[R.ch] == 0) continue;
     const int ev_first = event_first_hit(a, d, R.e);
-    const bool staged = R.total <= cap;
-    if (staged) {
-      for (int p = threadIdx.x; p < R.total; p += kWG) {
-        const int r = region_row_of(L, R.rh, p);
-        const int s = L.row_gs[r] + (p - L.row_lo[r]);
-        sx[p] = a.xs[s];
-        sy[p] = a.ys[s];
-        sr[p] = a.rho[s];
-        sh[p] = a.hs[s];
-      }
-      __syncthreads();
+    if (R.total <= g.lds_cap) {
+      nh_staged(g, a, d, R, L, rec, queue, &s_qn, ev_first, strict);
+      continue;
     }
-    for (int base = 0; base < nq; base += qpp) {  // uniform trip count
-      const int q = base + threadIdx.x / tpq;
-      const bool active = q < nq;
-      NhBest b{__int_as_float(0x7f800000), INT_MAX, -1};
-      int slot = 0, hi = 0;
-      float ri = 0.0f;
-      if (active) {
-        int row, p;
-        core_query(L, R, q, row, p);
-        slot = L.row_gs[row] + (p - L.row_lo[row]);
-        const float xi = a.xs[slot], yi = a.ys[slot];
-        ri = a.rho[slot];
-        hi = a.hs[slot];
-        const float wx = window_half(g.win_dm, xi), wy = window_half(g.win_dm, yi);
-        const int gx0 = tile_coord(__fsub_rn(xi, wx), g.x0, g.inv_t, g.nx);
-        const int gx1 = tile_coord(__fadd_rn(xi, wx), g.x0, g.inv_t, g.nx);
-        const int gy0 = tile_coord(__fsub_rn(yi, wy), g.y0, g.inv_t, g.ny);
-        const int gy1 = tile_coord(__fadd_rn(yi, wy), g.y0, g.inv_t, g.ny);
-        const bool inside = gx0 >= R.rx0 && gy0 >= R.ry0 && gx1 < R.rx0 + R.rw && gy1 < R.ry0 + R.rh;
-        if (staged && inside) {
-          for (int ty = gy0 - R.ry0; ty <= gy1 - R.ry0; ++ty) {
-            const int q0 = L.ts[ty * per_row + gx0 - R.rx0];
-            const int q1 = L.ts[ty * per_row + gx1 - R.rx0 + 1];
-            for (int c = q0 + sub; c < q1; c += tpq)
-              nh_consider(b, dist2(xi, yi, sx[c], sy[c]), sh[c], c, sr[c], ri, hi, g.dm2, strict);
-          }
-        } else {
-          if (staged) atomicOr(a.err, (uint32_t)E_WINDOW);
-          for (int ty = gy0; ty <= gy1; ++ty) {
-            const int64_t t = ubase + (int64_t)ty * g.nx;
-            const int s0 = a.tile_start[t + gx0], s1 = a.tile_start[t + gx1 + 1];
-            for (int c = s0 + sub; c < s1; c += tpq)
-              nh_consider(b, dist2(xi, yi, a.xs[c], a.ys[c]), a.hs[c], -2 - c, a.rho[c], ri, hi, g.dm2, strict);
-          }
-        }
+    for (int ty = ty0; ty <= ty1; ++ty)
+      for (int tx = tx0; tx <= tx1; ++tx) {
+        make_region(g, unit, tx, ty, tx, ty, R);
+        region_setup(g, a, R, L);
+        if (L.core_lo[R.ch] == 0) continue;
+        if (R.total <= g.lds_cap)
+          nh_staged(g, a, d, R, L, rec, queue, &s_qn, ev_first, strict);
+        else
+          nh_global_region(g, a, d, R, L, ev_first, strict);
       }
-      nh_reduce(b, tpq);
-      if (active && sub == 0) {
-        // position -> slot: LDS positions are >= 0, global slots are encoded as -2 - slot
-        if (b.p >= 0) {
-          const int r = region_row_of(L, R.rh, b.p);
-          b.p = L.row_gs[r] + (b.p - L.row_lo[r]);
-        } else if (b.p <= -2) {
-          b.p = -2 - b.p;
-        }
-        decide_and_store(g, a, d, slot, hi, ri, b, ev_first);
-      }
-    }
   }
 }
 
@@ -870,7 +1050,7 @@ __global__ void k_set_desc(RunDesc d, RunDesc* dd) {
 // ---------------------------------------------------------------------------
 // Host launches.
 // ---------------------------------------------------------------------------
-int lds_bytes_for(int lds_cap) { return lds_cap * 20; }
+int lds_bytes_for(int lds_cap) { return lds_cap * 20; }  // float4 record + one int per staged hit
 
 static inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
@@ -911,7 +1091,7 @@ static hipError_t launch_all(const Geom& g, const Arena& a, DescArg<G> dg, const
   else
     k_density<G, 3><<<g_items, kWG, lds, s>>>(dg, g, a);
   mark();
-  k_nearest_higher<G><<<g_items, kWG, g.lds_cap * 16, s>>>(dg, g, a);
+  k_nearest_higher<G><<<g_items, kWG, lds, s>>>(dg, g, a);
   mark();
   if (fol)
     k_scan<G, SCAN_SEEDS_FOLLOW><<<g_scan_s, kWG, 0, s>>>(dg, g, a);
