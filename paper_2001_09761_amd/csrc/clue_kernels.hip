@@ -127,29 +127,56 @@ __global__ __launch_bounds__(kWG) void k_clear(DescArg<G> dg, Geom g, Arena a) {
 
 // ---------------------------------------------------------------------------
 // k_hist: tile of every hit, atomic count per tile, arrival rank kept.
+// Lanes of a wave that share a tile are grouped first, so each distinct tile
+// costs one atomic per wave (hits of a cluster tend to be adjacent in input
+// order); ranks within a group follow lane order.
 // ---------------------------------------------------------------------------
 template <bool G>
 __global__ __launch_bounds__(kWG) void k_hist(DescArg<G> dg, Geom g, Arena a) {
   const RunDesc d = dg.get();
   const int stride = gridDim.x * kWG;
-  for (int h = blockIdx.x * kWG + threadIdx.x; h < d.n; h += stride) {
-    int e = 0;
-    if (d.event) {
-      e = clampi(d.event[h], 0, d.n_events - 1);
-      const int prev = h == 0 ? -1 : clampi(d.event[h - 1], 0, d.n_events - 1);
-      for (int k = prev + 1; k <= e; ++k) a.ev_start[k] = h;
-      if (h == d.n - 1)
-        for (int k = e + 1; k <= d.n_events; ++k) a.ev_start[k] = d.n;
-    } else if (h == 0) {
-      a.ev_start[0] = 0;
-      a.ev_start[1] = d.n;
+  const int lane = threadIdx.x & 63;
+  for (int h0 = blockIdx.x * kWG; h0 < d.n; h0 += stride) {  // uniform per workgroup
+    const int h = h0 + (int)threadIdx.x;
+    const bool valid = h < d.n;
+    int t = -1;
+    if (valid) {
+      int e = 0;
+      if (d.event) {
+        e = clampi(d.event[h], 0, d.n_events - 1);
+        const int prev = h == 0 ? -1 : clampi(d.event[h - 1], 0, d.n_events - 1);
+        for (int k = prev + 1; k <= e; ++k) a.ev_start[k] = h;
+        if (h == d.n - 1)
+          for (int k = e + 1; k <= d.n_events; ++k) a.ev_start[k] = d.n;
+      } else if (h == 0) {
+        a.ev_start[0] = 0;
+        a.ev_start[1] = d.n;
+      }
+      const int l = clampi(d.layer[h], 0, g.L - 1);
+      const int tx = tile_coord(d.x[h], g.x0, g.inv_t, g.nx);
+      const int ty = tile_coord(d.y[h], g.y0, g.inv_t, g.ny);
+      t = (e * g.L + l) * g.tpl + ty * g.nx + tx;
     }
-    const int l = clampi(d.layer[h], 0, g.L - 1);
-    const int tx = tile_coord(d.x[h], g.x0, g.inv_t, g.nx);
-    const int ty = tile_coord(d.y[h], g.y0, g.inv_t, g.ny);
-    const int t = (e * g.L + l) * g.tpl + ty * g.nx + tx;
-    a.key[h] = t;
-    a.rank[h] = atomicAdd(&a.tile_start[t], 1);
+    unsigned long long todo = __ballot(valid);
+    int leader = lane, off = 0, cnt = 0;
+    while (todo) {  // wave-uniform: one pass per distinct tile in the wave
+      const int l = __ffsll((long long)todo) - 1;
+      const int lt = __shfl(t, l, 64);
+      const unsigned long long peers = __ballot(t == lt) & todo;
+      if ((peers >> lane) & 1ull) {
+        leader = l;
+        off = __popcll(peers & ((1ull << lane) - 1ull));
+      }
+      if (lane == l) cnt = __popcll(peers);
+      todo &= ~peers;
+    }
+    int base = 0;
+    if (valid && lane == leader) base = atomicAdd(&a.tile_start[t], cnt);
+    base = __shfl(base, leader, 64);
+    if (valid) {
+      a.key[h] = t;
+      a.rank[h] = base + off;
+    }
   }
 }
 
@@ -541,23 +568,35 @@ __device__ float density_merge_full(const float4* __restrict__ rec, const int* l
   return acc;
 }
 
+// Lowest set bit of a 64-bit mask kept as two 32-bit halves.
+__device__ __forceinline__ int lowbit64(unsigned lo, unsigned hi) {
+  return lo ? __builtin_ctz(lo) : 32 + __builtin_ctz(hi);
+}
+
 template <int MAXL>
 __device__ __forceinline__ float density_two_pass(const float4* __restrict__ rec, const int* lo, const int* hi,
                                                   float xi, float yi, float dc2) {
   constexpr int K = MAXL * MAXL;
-  unsigned long long msk[K];
+  unsigned mlo[K], mhi[K];
   bool big = false;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    msk[k] = 0ull;
+    mlo[k] = 0u;
+    mhi[k] = 0u;
     const int len = hi[k] - lo[k];
     big |= len > 64;
-    const int n = min(len, 64);
     const float4* base = rec + lo[k];
+    const int n0 = min(len, 32);
 #pragma unroll 4
-    for (int c = 0; c < n; ++c) {
+    for (int c = 0; c < n0; ++c) {
       const float2 q = *reinterpret_cast<const float2*>(base + c);
-      if (dist2(xi, yi, q.x, q.y) < dc2) msk[k] |= 1ull << c;
+      mlo[k] |= (dist2(xi, yi, q.x, q.y) < dc2 ? 1u : 0u) << c;
+    }
+    const int n1 = min(len, 64);
+#pragma unroll 4
+    for (int c = 32; c < n1; ++c) {
+      const float2 q = *reinterpret_cast<const float2*>(base + c);
+      mhi[k] |= (dist2(xi, yi, q.x, q.y) < dc2 ? 1u : 0u) << (c - 32);
     }
   }
   if (big) return density_merge_full<MAXL>(rec, lo, hi, xi, yi, dc2);
@@ -567,8 +606,8 @@ __device__ __forceinline__ float density_two_pass(const float4* __restrict__ rec
   for (int k = 0; k < K; ++k) {
     hh[k] = INT_MAX;
     ee[k] = 0.0f;
-    if (msk[k]) {
-      const float4 r = rec[lo[k] + __ffsll((long long)msk[k]) - 1];
+    if (mlo[k] | mhi[k]) {
+      const float4 r = rec[lo[k] + lowbit64(mlo[k], mhi[k])];
       hh[k] = __float_as_int(r.w);
       ee[k] = r.z;
     }
@@ -579,22 +618,32 @@ __device__ __forceinline__ float density_two_pass(const float4* __restrict__ rec
 #pragma unroll
     for (int k = 1; k < K; ++k) m = min(m, hh[k]);
     if (m == INT_MAX) break;
-    float e = 0.0f;
-    int np = -1;
+    // the selected list: take its head, drop its lowest passing bit
+    float e = ee[0];
+    unsigned ml = mlo[0], mh = mhi[0];
+    int base = lo[0];
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
+    for (int k = 1; k < K; ++k) {
       if (hh[k] == m) {
         e = ee[k];
-        msk[k] &= msk[k] - 1ull;
-        np = msk[k] ? lo[k] + __ffsll((long long)msk[k]) - 1 : -1;
+        ml = mlo[k];
+        mh = mhi[k];
+        base = lo[k];
       }
     }
     acc = __fadd_rn(acc, e);
+    if (ml)
+      ml &= ml - 1u;
+    else
+      mh &= mh - 1u;
+    const bool more = (ml | mh) != 0u;
     float4 r = make_float4(0.0f, 0.0f, 0.0f, __int_as_float(INT_MAX));
-    if (np >= 0) r = rec[np];
+    if (more) r = rec[base + lowbit64(ml, mh)];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       if (hh[k] == m) {
+        mlo[k] = ml;
+        mhi[k] = mh;
         hh[k] = __float_as_int(r.w);
         ee[k] = r.z;
       }
@@ -753,32 +802,43 @@ __global__ __launch_bounds__(kWG) void k_density(DescArg<G> dg, Geom g, Arena a)
 // over the full d_m window with `tpq` lanes each (phase 2).
 // Records: (x, y, rho, hit index as bits).
 // ---------------------------------------------------------------------------
+// Order-preserving map of a float to uint32 (-0 folds onto +0), so that
+// (rho, index) compares as one 64-bit unsigned key.
+__device__ __forceinline__ unsigned ord_f32(float v) {
+  const unsigned u = __float_as_uint(__fadd_rn(v, 0.0f));
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ unsigned long long key64(unsigned hi, unsigned lo) {
+  return ((unsigned long long)hi << 32) | lo;
+}
+
 struct NhBest {
-  float d2;
-  int h;  // caller index of the nearest-higher (INT_MAX: none)
-  int p;  // its position: LDS position >= 0, global slot s encoded as -2 - s, -1 none
+  unsigned long long k;  // (d2 bits, caller index); ~0: none
+  int p;                 // LDS position >= 0, or global slot s encoded as -2 - s; -1 none
+  __device__ __forceinline__ float d2() const { return __uint_as_float((unsigned)(k >> 32)); }
+  __device__ __forceinline__ int h() const { return (int)(unsigned)(k & 0xffffffffu); }
 };
 
-__device__ __forceinline__ void nh_consider(NhBest& b, float d2, int hq, int pq, float rq, float ri, int hi,
-                                            float dm2, bool strict) {
-  if (d2 < dm2) {
-    const bool higher = rq > ri || (!strict && rq == ri && hq > hi);
-    if (higher && (d2 < b.d2 || (d2 == b.d2 && hq < b.h))) {
-      b.d2 = d2;
-      b.h = hq;
-      b.p = pq;
-    }
+// One candidate j for query i: eligible when d2 < thr and j is higher
+// (ordr/h keys); keeps the lexicographic minimum of (d2, index). d2 >= 0,
+// so its bit pattern orders like its value.
+template <bool STRICT>
+__device__ __forceinline__ void nh_consider(NhBest& b, float d2, unsigned ordj, unsigned hj, int pq, unsigned ordi,
+                                            unsigned hi, float thr) {
+  const bool higher = STRICT ? ordj > ordi : key64(ordj, hj) > key64(ordi, hi);
+  const unsigned long long ck = key64(__float_as_uint(d2), hj);
+  if (d2 < thr && higher && ck < b.k) {
+    b.k = ck;
+    b.p = pq;
   }
 }
 
 __device__ __forceinline__ void nh_reduce(NhBest& b, int tpq) {
   for (int o = 1; o < tpq; o <<= 1) {
-    const float od = __shfl_xor(b.d2, o, 64);
-    const int oh = __shfl_xor(b.h, o, 64);
+    const unsigned long long ok = __shfl_xor(b.k, o, 64);
     const int op = __shfl_xor(b.p, o, 64);
-    if (od < b.d2 || (od == b.d2 && oh < b.h)) {
-      b.d2 = od;
-      b.h = oh;
+    if (ok < b.k) {
+      b.k = ok;
       b.p = op;
     }
   }
@@ -789,63 +849,77 @@ __device__ __forceinline__ void nh_reduce(NhBest& b, int tpq) {
 __device__ __forceinline__ void decide_and_store(const Geom& g, const Arena& a, const RunDesc& d, int slot, int hi,
                                                  float ri, const NhBest& b, int ev_first) {
   const bool has = b.p >= 0;
-  const float d2 = has ? b.d2 : __int_as_float(0x7f800000);
+  const float d2 = has ? b.d2() : __int_as_float(0x7f800000);
   const bool seed = ri > g.rho_c && d2 > g.dcs2;
   const bool outlier = ri < g.rho_c && d2 > g.do2;
   const bool follower = !seed && !outlier && has;
   a.parent[slot] = follower ? b.p : slot;
   a.flags[slot] = (uint8_t)((seed ? F_SEED : 0) | (outlier ? F_OUTLIER : 0) | (follower ? F_FOLLOWER : 0));
   d.is_seed[hi] = seed ? 1 : 0;
-  if (follower && !(g.flags & 8u)) a.frank[slot] = atomicAdd(&a.fstart[b.h], 1);
+  if (follower && !(g.flags & 8u)) a.frank[slot] = atomicAdd(&a.fstart[b.h()], 1);
   if (g.flags & 2u) {
-    a.nh_out[hi] = has ? b.h - ev_first : -1;
+    a.nh_out[hi] = has ? b.h() - ev_first : -1;
     a.d2_out[hi] = d2;
   }
 }
 
 // Scans window tiles [tx0..tx1] x [ty0..ty1] (region coordinates) of the
-// staged records with lanes sub, sub + step, ...
+// staged records (x, y, ord(rho), index) with lanes sub, sub + step, ...
+template <bool STRICT>
 __device__ __forceinline__ void nh_scan_staged(const float4* __restrict__ rec, const RegionLds& L, int per_row,
                                                int tx0, int tx1, int ty0, int ty1, int sub, int step, float xi,
-                                               float yi, float ri, int hi, float dm2, bool strict, NhBest& b) {
+                                               float yi, unsigned ordi, unsigned hi, float thr, NhBest& b) {
   for (int ty = ty0; ty <= ty1; ++ty) {
     const int q0 = L.ts[ty * per_row + tx0];
     const int q1 = L.ts[ty * per_row + tx1 + 1];
 #pragma unroll 4
     for (int c = q0 + sub; c < q1; c += step) {
       const float4 r = rec[c];
-      nh_consider(b, dist2(xi, yi, r.x, r.y), __float_as_int(r.w), c, r.z, ri, hi, dm2, strict);
+      nh_consider<STRICT>(b, dist2(xi, yi, r.x, r.y), __float_as_uint(r.z), __float_as_uint(r.w), c, ordi, hi, thr);
     }
   }
 }
 
+template <bool STRICT>
+__device__ void nh_global_scan(const Geom& g, const Arena& a, int64_t ubase, const Window& W, int sub, int step,
+                               float xi, float yi, unsigned ordi, unsigned hi, NhBest& b) {
+  for (int ty = W.y0; ty <= W.y1; ++ty) {
+    const int64_t t = ubase + (int64_t)ty * g.nx;
+    const int s0 = a.tile_start[t + W.x0], s1 = a.tile_start[t + W.x1 + 1];
+    for (int c = s0 + sub; c < s1; c += step)
+      nh_consider<STRICT>(b, dist2(xi, yi, a.xs[c], a.ys[c]), ord_f32(a.rho[c]), (unsigned)a.hs[c], -2 - c, ordi,
+                          hi, g.dm2);
+  }
+}
+
+template <bool STRICT>
 __device__ void nh_staged(const Geom& g, const Arena& a, const RunDesc& d, const Region& R, const RegionLds& L,
-                          float4* rec, int* queue, int* s_qn, int ev_first, bool strict) {
+                          float4* rec, int* queue, int* s_qn, int ev_first) {
   const int per_row = R.rw + 1;
   const int64_t ubase = (int64_t)R.unit * g.tpl;
   for (int p = threadIdx.x; p < R.total; p += kWG) {
     const int s = slot_of(L, region_row_of(L, R.rh, p), p);
-    rec[p] = make_float4(a.xs[s], a.ys[s], a.rho[s], __int_as_float(a.hs[s]));
+    rec[p] = make_float4(a.xs[s], a.ys[s], __uint_as_float(ord_f32(a.rho[s])), __int_as_float(a.hs[s]));
   }
   if (threadIdx.x == 0) *s_qn = 0;
   __syncthreads();
   const int nq = L.core_lo[R.ch];
-  // phase 1: radius r1
+  // phase 1: radius r1; only hits strictly within r1 can settle a query here
   for (int q = threadIdx.x; q < nq; q += kWG) {
     bool done = false;
     if (g.nh_phase1) {
       int row, p;
       core_query(L, R, q, row, p);
       const float4 me = rec[p];
-      const int hi = __float_as_int(me.w);
+      const unsigned ordi = __float_as_uint(me.z), hi = __float_as_uint(me.w);
       const Window W = query_window(g, g.win_r1, me.x, me.y);
       const int tx0 = W.x0 - R.rx0, tx1 = W.x1 - R.rx0, ty0 = W.y0 - R.ry0, ty1 = W.y1 - R.ry0;
       if (tx0 >= 0 && ty0 >= 0 && tx1 < R.rw && ty1 < R.rh) {
-        NhBest b{__int_as_float(0x7f800000), INT_MAX, -1};
-        nh_scan_staged(rec, L, per_row, tx0, tx1, ty0, ty1, 0, 1, me.x, me.y, me.z, hi, g.dm2, strict, b);
-        if (b.p >= 0 && b.d2 < g.r1sq) {
+        NhBest b{~0ull, -1};
+        nh_scan_staged<STRICT>(rec, L, per_row, tx0, tx1, ty0, ty1, 0, 1, me.x, me.y, ordi, hi, g.r1sq, b);
+        if (b.p >= 0) {
           b.p = slot_of(L, region_row_of(L, R.rh, b.p), b.p);
-          decide_and_store(g, a, d, slot_of(L, row, p), hi, me.z, b, ev_first);
+          decide_and_store(g, a, d, slot_of(L, row, p), (int)hi, a.rho[slot_of(L, row, p)], b, ev_first);
           done = true;
         }
       }
@@ -861,28 +935,23 @@ __device__ void nh_staged(const Geom& g, const Arena& a, const RunDesc& d, const
   for (int base = 0; base < nu; base += qpp) {  // uniform trip count
     const int qi = base + threadIdx.x / tpq;
     const bool active = qi < nu;
-    NhBest b{__int_as_float(0x7f800000), INT_MAX, -1};
-    int slot = 0, hi = 0;
-    float ri = 0.0f;
+    NhBest b{~0ull, -1};
+    int slot = 0;
+    unsigned hi = 0;
     if (active) {
       int row, p;
       core_query(L, R, queue[qi], row, p);
       slot = slot_of(L, row, p);
       const float4 me = rec[p];
-      ri = me.z;
-      hi = __float_as_int(me.w);
+      const unsigned ordi = __float_as_uint(me.z);
+      hi = __float_as_uint(me.w);
       const Window W = query_window(g, g.win_dm, me.x, me.y);
       const int tx0 = W.x0 - R.rx0, tx1 = W.x1 - R.rx0, ty0 = W.y0 - R.ry0, ty1 = W.y1 - R.ry0;
       if (tx0 >= 0 && ty0 >= 0 && tx1 < R.rw && ty1 < R.rh) {
-        nh_scan_staged(rec, L, per_row, tx0, tx1, ty0, ty1, sub, tpq, me.x, me.y, ri, hi, g.dm2, strict, b);
+        nh_scan_staged<STRICT>(rec, L, per_row, tx0, tx1, ty0, ty1, sub, tpq, me.x, me.y, ordi, hi, g.dm2, b);
       } else {
         atomicOr(a.err, (uint32_t)E_WINDOW);
-        for (int ty = W.y0; ty <= W.y1; ++ty) {
-          const int64_t t = ubase + (int64_t)ty * g.nx;
-          const int s0 = a.tile_start[t + W.x0], s1 = a.tile_start[t + W.x1 + 1];
-          for (int c = s0 + sub; c < s1; c += tpq)
-            nh_consider(b, dist2(me.x, me.y, a.xs[c], a.ys[c]), a.hs[c], -2 - c, a.rho[c], ri, hi, g.dm2, strict);
-        }
+        nh_global_scan<STRICT>(g, a, ubase, W, sub, tpq, me.x, me.y, ordi, hi, b);
       }
     }
     nh_reduce(b, tpq);
@@ -891,13 +960,14 @@ __device__ void nh_staged(const Geom& g, const Arena& a, const RunDesc& d, const
         b.p = slot_of(L, region_row_of(L, R.rh, b.p), b.p);
       else if (b.p <= -2)
         b.p = -2 - b.p;
-      decide_and_store(g, a, d, slot, hi, ri, b, ev_first);
+      decide_and_store(g, a, d, slot, (int)hi, a.rho[slot], b, ev_first);
     }
   }
 }
 
-__device__ void nh_global_region(const Geom& g, const Arena& a, const RunDesc& d, const Region& R, const RegionLds& L,
-                                 int ev_first, bool strict) {
+template <bool STRICT>
+__device__ void nh_global_region(const Geom& g, const Arena& a, const RunDesc& d, const Region& R,
+                                 const RegionLds& L, int ev_first) {
   const int64_t ubase = (int64_t)R.unit * g.tpl;
   const int nq = L.core_lo[R.ch];
   const int tpq = g.tpq;
@@ -906,30 +976,50 @@ __device__ void nh_global_region(const Geom& g, const Arena& a, const RunDesc& d
   for (int base = 0; base < nq; base += qpp) {
     const int q = base + threadIdx.x / tpq;
     const bool active = q < nq;
-    NhBest b{__int_as_float(0x7f800000), INT_MAX, -1};
-    int slot = 0, hi = 0;
-    float ri = 0.0f;
+    NhBest b{~0ull, -1};
+    int slot = 0;
+    unsigned hi = 0;
     if (active) {
       int row, p;
       core_query(L, R, q, row, p);
       slot = slot_of(L, row, p);
       const float xi = a.xs[slot], yi = a.ys[slot];
-      ri = a.rho[slot];
-      hi = a.hs[slot];
+      hi = (unsigned)a.hs[slot];
       const Window W = query_window(g, g.win_dm, xi, yi);
-      for (int ty = W.y0; ty <= W.y1; ++ty) {
-        const int64_t t = ubase + (int64_t)ty * g.nx;
-        const int s0 = a.tile_start[t + W.x0], s1 = a.tile_start[t + W.x1 + 1];
-        for (int c = s0 + sub; c < s1; c += tpq)
-          nh_consider(b, dist2(xi, yi, a.xs[c], a.ys[c]), a.hs[c], -2 - c, a.rho[c], ri, hi, g.dm2, strict);
-      }
+      nh_global_scan<STRICT>(g, a, ubase, W, sub, tpq, xi, yi, ord_f32(a.rho[slot]), hi, b);
     }
     nh_reduce(b, tpq);
     if (active && sub == 0) {
       if (b.p <= -2) b.p = -2 - b.p;
-      decide_and_store(g, a, d, slot, hi, ri, b, ev_first);
+      decide_and_store(g, a, d, slot, (int)hi, a.rho[slot], b, ev_first);
     }
   }
+}
+
+template <bool STRICT>
+__device__ void nh_item(const Geom& g, const Arena& a, const RunDesc& d, int item, RegionLds& L, float4* rec,
+                        int* queue, int* s_qn) {
+  int unit, tx0, ty0, tx1, ty1;
+  item_block(g, item, unit, tx0, ty0, tx1, ty1);
+  Region R;
+  make_region(g, unit, tx0, ty0, tx1, ty1, R);
+  region_setup(g, a, R, L);
+  if (L.core_lo[R.ch] == 0) return;
+  const int ev_first = event_first_hit(a, d, R.e);
+  if (R.total <= g.lds_cap) {
+    nh_staged<STRICT>(g, a, d, R, L, rec, queue, s_qn, ev_first);
+    return;
+  }
+  for (int ty = ty0; ty <= ty1; ++ty)
+    for (int tx = tx0; tx <= tx1; ++tx) {
+      make_region(g, unit, tx, ty, tx, ty, R);
+      region_setup(g, a, R, L);
+      if (L.core_lo[R.ch] == 0) continue;
+      if (R.total <= g.lds_cap)
+        nh_staged<STRICT>(g, a, d, R, L, rec, queue, s_qn, ev_first);
+      else
+        nh_global_region<STRICT>(g, a, d, R, L, ev_first);
+    }
 }
 
 template <bool G>
@@ -946,27 +1036,10 @@ __global__ __launch_bounds__(kWG) void k_nearest_higher(DescArg<G> dg, Geom g, A
   for (;;) {
     const int item = pop_item(&a.counters[C_QUEUE_NH], &s_item);
     if (item >= n_items) break;
-    int unit, tx0, ty0, tx1, ty1;
-    item_block(g, item, unit, tx0, ty0, tx1, ty1);
-    Region R;
-    make_region(g, unit, tx0, ty0, tx1, ty1, R);
-    region_setup(g, a, R, L);
-    if (L.core_lo[R.ch] == 0) continue;
-    const int ev_first = event_first_hit(a, d, R.e);
-    if (R.total <= g.lds_cap) {
-      nh_staged(g, a, d, R, L, rec, queue, &s_qn, ev_first, strict);
-      continue;
-    }
-    for (int ty = ty0; ty <= ty1; ++ty)
-      for (int tx = tx0; tx <= tx1; ++tx) {
-        make_region(g, unit, tx, ty, tx, ty, R);
-        region_setup(g, a, R, L);
-        if (L.core_lo[R.ch] == 0) continue;
-        if (R.total <= g.lds_cap)
-          nh_staged(g, a, d, R, L, rec, queue, &s_qn, ev_first, strict);
-        else
-          nh_global_region(g, a, d, R, L, ev_first, strict);
-      }
+    if (strict)
+      nh_item<true>(g, a, d, item, L, rec, queue, &s_qn);
+    else
+      nh_item<false>(g, a, d, item, L, rec, queue, &s_qn);
   }
 }
 
