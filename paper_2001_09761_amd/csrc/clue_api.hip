@@ -81,8 +81,8 @@ static int plan_geom(const clue_params& p, float tile, int tpq, int bx, int by, 
     msg = "threads_per_query must be 1, 2, 4 or 8";
     return CLUE_ERR_ARG;
   }
-  if (bx < 1 || by < 1 || bx > 32 || by > 32) {
-    msg = "tile block must be within 1..32 tiles per side";
+  if (bx < 1 || by < 1 || bx > 16 || by > 16) {
+    msg = "tile block must be within 1..16 tiles per side";
     return CLUE_ERR_ARG;
   }
   if (lds_cap < 64 || lds_cap > kMaxLdsCap) {
@@ -252,7 +252,7 @@ static void drop_graph(clue_ctx* c) {
 
 static void compute_cfg(clue_ctx* c) {
   const int lds = lds_bytes_for(c->g.lds_cap);
-  const int occ_items = std::min(occupancy_blocks_per_cu(1, lds), occupancy_blocks_per_cu(3, c->g.lds_cap * 16));
+  const int occ_items = std::min(occupancy_blocks_per_cu(1, lds), occupancy_blocks_per_cu(3, lds_bytes_nh(c->g.lds_cap)));
   c->cfg.persist_blocks_stream = c->n_cu * std::min(occupancy_blocks_per_cu(0, 0), 8);
   c->cfg.persist_blocks_items = c->n_cu * std::max(1, occ_items);
   c->cfg.persist_blocks_scan = c->n_cu * std::min(occupancy_blocks_per_cu(2, 0), 4);

@@ -12,6 +12,7 @@ constexpr int kScanItems = 16;      // elements per thread in the prefix scans
 constexpr int kScanChunk = kWG * kScanItems;
 constexpr int kMaxRegionTiles = 640;   // staged region tiles, rows x (cols + 1), per workgroup
 constexpr int kMaxRegionRows = 64;
+constexpr int kMaxQuads = 289;        // (block + 1)^2 quads for blocks up to 16x16 tiles
 constexpr int kDefaultLdsCap = 1024;   // staged hits per workgroup (fast path)
 constexpr int kMaxLdsCap = 2048;
 
@@ -124,5 +125,6 @@ hipError_t launch_set_desc(const RunDesc& d, RunDesc* dd, hipStream_t s);
 hipError_t launch_validate(const Geom& g, const Arena& a, const RunDesc& d, hipStream_t s);
 int occupancy_blocks_per_cu(int which, int lds_bytes);
 int lds_bytes_for(int lds_cap);
+int lds_bytes_nh(int lds_cap);
 
 }  // namespace clue

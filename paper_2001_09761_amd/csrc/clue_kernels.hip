@@ -412,6 +412,8 @@ struct RegionLds {
   int row_gs[kMaxRegionRows];
   int row_lo[kMaxRegionRows + 1];
   int core_lo[kMaxRegionRows + 1];
+  int qoff[kMaxQuads + 1];  // density: offsets of the merged 2x2-tile lists
+  int qtotal;
 };
 
 __device__ __forceinline__ void item_block(const Geom& g, int item, int& unit, int& tx0, int& ty0, int& tx1,
@@ -680,9 +682,16 @@ __device__ float density_global(const Geom& g, const Arena& a, int64_t ubase, fl
   return acc;
 }
 
+// Density over a staged region. Tiles are sorted by hit index in LDS
+// (records x, y, E, index). With MAXL == 2 every query window lies inside the
+// 2x2 tile quad anchored at its lower-left window tile; the quads a core
+// query can use are merged once per region into index-ordered lists (LDS
+// indices into the sorted records), so each query is one linear scan in
+// ascending hit index. Otherwise (or if the quads do not fit) a query merges
+// its window's tile lists itself.
 template <int MAXL>
-__device__ void density_staged(const Geom& g, const Arena& a, const Region& R, const RegionLds& L, float4* rec,
-                               int* stmp, bool keep) {
+__device__ void density_staged(const Geom& g, const Arena& a, const Region& R, RegionLds& L, float4* rec, int* stmp,
+                               unsigned short* stile, unsigned short* qidx, bool keep) {
   const int per_row = R.rw + 1;
   const int64_t ubase = (int64_t)R.unit * g.tpl;
   for (int p = threadIdx.x; p < R.total; p += kWG) {
@@ -707,8 +716,72 @@ __device__ void density_staged(const Geom& g, const Arena& a, const Region& R, c
     for (int q = t0; q < t1; ++q) rk += stmp[q] < hp;
     const int slot = slot_of(L, lo / per_row, p);
     rec[t0 + rk] = make_float4(a.xs[slot], a.ys[slot], a.es[slot], __int_as_float(hp));
+    stile[t0 + rk] = (unsigned short)lo;
+  }
+  // quads anchored at region tiles [qx0, qx1] x [qy0, qy1]
+  const int qx0 = max(R.cx0 - 1, 0), qx1 = min(R.cx0 + R.cw - 1, R.rw - 1);
+  const int qy0 = max(R.cy0 - 1, 0), qy1 = min(R.cy0 + R.ch - 1, R.rh - 1);
+  const int qw = qx1 - qx0 + 1;
+  const int nquad = qw * (qy1 - qy0 + 1);
+  bool use_quads = MAXL == 2 && nquad <= kMaxQuads;
+  if (use_quads) {
+    if (threadIdx.x < 64) {
+      // quad sizes -> offsets, 64 quads per wave step
+      int run = 0;
+      for (int q0 = 0; q0 < nquad; q0 += 64) {
+        const int q = q0 + (int)threadIdx.x;
+        int len = 0;
+        if (q < nquad) {
+          const int ax = qx0 + q % qw, ay = qy0 + q / qw;
+          const int bx1 = min(ax + 1, R.rw - 1), by1 = min(ay + 1, R.rh - 1);
+          for (int ty = ay; ty <= by1; ++ty) len += L.ts[ty * per_row + bx1 + 1] - L.ts[ty * per_row + ax];
+        }
+        const int incl = wave_incl_scan(len, threadIdx.x);
+        if (q < nquad) L.qoff[q] = run + incl - len;
+        run += __shfl(incl, 63, 64);
+      }
+      if (threadIdx.x == 0) {
+        L.qoff[nquad] = run;
+        L.qtotal = run;
+      }
+    }
   }
   __syncthreads();
+  if (use_quads && L.qtotal <= 4 * g.lds_cap) {
+    // place every sorted record into each quad that holds its tile
+    for (int p = threadIdx.x; p < R.total; p += kWG) {
+      const int tl = stile[p];
+      const int tr = tl / per_row, tc = tl - tr * per_row;
+      const int hp = __float_as_int(rec[p].w);
+      const int own = p - L.ts[tl];
+#pragma unroll
+      for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 2; ++dx) {
+          const int ax = tc - dx, ay = tr - dy;
+          if (ax < qx0 || ax > qx1 || ay < qy0 || ay > qy1) continue;
+          int pos = own;
+          const int bx1 = min(ax + 1, R.rw - 1), by1 = min(ay + 1, R.rh - 1);
+          for (int ty = ay; ty <= by1; ++ty)
+            for (int tx = ax; tx <= bx1; ++tx) {
+              if (ty == tr && tx == tc) continue;
+              int lo = L.ts[ty * per_row + tx], hi = L.ts[ty * per_row + tx + 1];
+              while (lo < hi) {  // count of entries with index < hp
+                const int mid = (lo + hi) >> 1;
+                if (__float_as_int(rec[mid].w) < hp)
+                  lo = mid + 1;
+                else
+                  hi = mid;
+              }
+              pos += lo - L.ts[ty * per_row + tx];
+            }
+          qidx[L.qoff[(ay - qy0) * qw + (ax - qx0)] + pos] = (unsigned short)p;
+        }
+    }
+    __syncthreads();
+  } else {
+    use_quads = false;
+  }
   const int nq = L.core_lo[R.ch];
   for (int q = threadIdx.x; q < nq; q += kWG) {
     int row, p;
@@ -718,23 +791,31 @@ __device__ void density_staged(const Geom& g, const Arena& a, const Region& R, c
     const Window W = query_window(g, g.win_dc, xi, yi);
     const int tx0 = W.x0 - R.rx0, tx1 = W.x1 - R.rx0, ty0 = W.y0 - R.ry0, ty1 = W.y1 - R.ry0;
     const bool ok = tx0 >= 0 && ty0 >= 0 && tx1 < R.rw && ty1 < R.rh && tx1 - tx0 < MAXL && ty1 - ty0 < MAXL;
-    int lo[MAXL * MAXL], hi[MAXL * MAXL];
-#pragma unroll
-    for (int jy = 0; jy < MAXL; ++jy)
-#pragma unroll
-      for (int jx = 0; jx < MAXL; ++jx) {
-        const int k = jy * MAXL + jx;
-        const int ty = ty0 + jy, tx = tx0 + jx;
-        if (ok && ty <= ty1 && tx <= tx1) {
-          lo[k] = L.ts[ty * per_row + tx];
-          hi[k] = L.ts[ty * per_row + tx + 1];
-        } else {
-          lo[k] = 0;
-          hi[k] = 0;
-        }
+    float rho = 0.0f;
+    if (ok && use_quads) {
+      const int qq = (ty0 - qy0) * qw + (tx0 - qx0);
+      const int c0 = L.qoff[qq], c1 = L.qoff[qq + 1];
+#pragma unroll 4
+      for (int c = c0; c < c1; ++c) {
+        const float4 r = rec[qidx[c]];
+        if (dist2(xi, yi, r.x, r.y) < g.dc2) rho = __fadd_rn(rho, r.z);
       }
-    float rho;
-    if (ok) {
+    } else if (ok) {
+      int lo[MAXL * MAXL], hi[MAXL * MAXL];
+#pragma unroll
+      for (int jy = 0; jy < MAXL; ++jy)
+#pragma unroll
+        for (int jx = 0; jx < MAXL; ++jx) {
+          const int k = jy * MAXL + jx;
+          const int ty = ty0 + jy, tx = tx0 + jx;
+          if (ty <= ty1 && tx <= tx1) {
+            lo[k] = L.ts[ty * per_row + tx];
+            hi[k] = L.ts[ty * per_row + tx + 1];
+          } else {
+            lo[k] = 0;
+            hi[k] = 0;
+          }
+        }
       rho = density_two_pass<MAXL>(rec, lo, hi, xi, yi, g.dc2);
     } else {
       atomicOr(a.err, (uint32_t)E_WINDOW);
@@ -766,6 +847,8 @@ __global__ __launch_bounds__(kWG) void k_density(DescArg<G> dg, Geom g, Arena a)
   __shared__ int s_item;
   float4* rec = reinterpret_cast<float4*>(smem);
   int* stmp = reinterpret_cast<int*>(rec + g.lds_cap);
+  unsigned short* stile = reinterpret_cast<unsigned short*>(stmp + g.lds_cap);
+  unsigned short* qidx = stile + g.lds_cap;
   const int n_items = d.n_events * g.L * g.bpu;
   const bool keep = g.flags & 2u;
   for (;;) {
@@ -778,7 +861,7 @@ __global__ __launch_bounds__(kWG) void k_density(DescArg<G> dg, Geom g, Arena a)
     region_setup(g, a, R, L);
     if (L.core_lo[R.ch] == 0) continue;
     if (R.total <= g.lds_cap) {
-      density_staged<MAXL>(g, a, R, L, rec, stmp, keep);
+      density_staged<MAXL>(g, a, R, L, rec, stmp, stile, qidx, keep);
       continue;
     }
     for (int ty = ty0; ty <= ty1; ++ty)
@@ -787,7 +870,7 @@ __global__ __launch_bounds__(kWG) void k_density(DescArg<G> dg, Geom g, Arena a)
         region_setup(g, a, R, L);
         if (L.core_lo[R.ch] == 0) continue;
         if (R.total <= g.lds_cap)
-          density_staged<MAXL>(g, a, R, L, rec, stmp, keep);
+          density_staged<MAXL>(g, a, R, L, rec, stmp, stile, qidx, keep);
         else
           density_global_region(g, a, R, L, keep);
       }
@@ -1123,7 +1206,11 @@ __global__ void k_set_desc(RunDesc d, RunDesc* dd) {
 // ---------------------------------------------------------------------------
 // Host launches.
 // ---------------------------------------------------------------------------
-int lds_bytes_for(int lds_cap) { return lds_cap * 20; }  // float4 record + one int per staged hit
+// Dynamic LDS of the tile-block kernels: per staged hit a float4 record, an
+// int and a 16-bit tile id, plus four 16-bit quad-list entries.
+int lds_bytes_for(int lds_cap) { return lds_cap * (16 + 4 + 2 + 8); }
+// Nearest-higher: per staged hit a float4 record and one queue int.
+int lds_bytes_nh(int lds_cap) { return lds_cap * (16 + 4); }
 
 static inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
@@ -1164,7 +1251,7 @@ static hipError_t launch_all(const Geom& g, const Arena& a, DescArg<G> dg, const
   else
     k_density<G, 3><<<g_items, kWG, lds, s>>>(dg, g, a);
   mark();
-  k_nearest_higher<G><<<g_items, kWG, lds, s>>>(dg, g, a);
+  k_nearest_higher<G><<<g_items, kWG, lds_bytes_nh(g.lds_cap), s>>>(dg, g, a);
   mark();
   if (fol)
     k_scan<G, SCAN_SEEDS_FOLLOW><<<g_scan_s, kWG, 0, s>>>(dg, g, a);
