@@ -252,9 +252,9 @@ static void drop_graph(clue_ctx* c) {
 
 static void compute_cfg(clue_ctx* c) {
   const int lds = lds_bytes_for(c->g.lds_cap);
-  const int occ_items = std::min(occupancy_blocks_per_cu(1, lds), occupancy_blocks_per_cu(3, lds_bytes_nh(c->g.lds_cap)));
   c->cfg.persist_blocks_stream = c->n_cu * std::min(occupancy_blocks_per_cu(0, 0), 8);
-  c->cfg.persist_blocks_items = c->n_cu * std::max(1, occ_items);
+  c->cfg.persist_blocks_rho = c->n_cu * occupancy_blocks_per_cu(1, lds);
+  c->cfg.persist_blocks_nh = c->n_cu * occupancy_blocks_per_cu(3, lds_bytes_nh(c->g.lds_cap));
   c->cfg.persist_blocks_scan = c->n_cu * std::min(occupancy_blocks_per_cu(2, 0), 4);
 }
 

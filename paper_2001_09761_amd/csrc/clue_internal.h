@@ -112,7 +112,8 @@ extern const char* const kStageNames[S_COUNT];
 struct LaunchCfg {
   bool graph_mode;   // persistent kernels reading the descriptor from device memory
   int persist_blocks_stream;  // persistent grid of the streaming kernels
-  int persist_blocks_items;   // persistent grid of the tile-block kernels
+  int persist_blocks_rho;     // persistent grid of the density kernel
+  int persist_blocks_nh;      // persistent grid of the nearest-higher kernel
   int persist_blocks_scan;    // persistent grid of the scans
 };
 

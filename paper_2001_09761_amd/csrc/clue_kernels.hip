@@ -1228,7 +1228,8 @@ static hipError_t launch_all(const Geom& g, const Arena& a, DescArg<G> dg, const
   };
   const int g_clear = G ? cfg.persist_blocks_stream
                         : (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(std::max(tt, n + 1), kWG), 1 << 16));
-  const int g_items = G ? cfg.persist_blocks_items : (int)std::max<int64_t>(1, items);
+  const int g_rho = G ? cfg.persist_blocks_rho : (int)std::max<int64_t>(1, items);
+  const int g_nh = G ? cfg.persist_blocks_nh : (int)std::max<int64_t>(1, items);
   const int g_scan_t = G ? cfg.persist_blocks_scan : cdiv(tt, kScanChunk);
   const int g_scan_s = G ? cfg.persist_blocks_scan : cdiv(n + 1, kScanChunk);
   const bool fol = !(g.flags & 8u);
@@ -1247,11 +1248,11 @@ static hipError_t launch_all(const Geom& g, const Arena& a, DescArg<G> dg, const
   mark();
   const int lds = lds_bytes_for(g.lds_cap);
   if (g.maxl == 2)
-    k_density<G, 2><<<g_items, kWG, lds, s>>>(dg, g, a);
+    k_density<G, 2><<<g_rho, kWG, lds, s>>>(dg, g, a);
   else
-    k_density<G, 3><<<g_items, kWG, lds, s>>>(dg, g, a);
+    k_density<G, 3><<<g_rho, kWG, lds, s>>>(dg, g, a);
   mark();
-  k_nearest_higher<G><<<g_items, kWG, lds_bytes_nh(g.lds_cap), s>>>(dg, g, a);
+  k_nearest_higher<G><<<g_nh, kWG, lds_bytes_nh(g.lds_cap), s>>>(dg, g, a);
   mark();
   if (fol)
     k_scan<G, SCAN_SEEDS_FOLLOW><<<g_scan_s, kWG, 0, s>>>(dg, g, a);
