@@ -1,0 +1,159 @@
+"""Autotuner for the batched form.
+
+Sweeps the kernel tuning (tile size, tile-block shape, LDS budget, lanes per
+full-window nearest-higher query, first nearest-higher radius and the density
+strategy) by coordinate descent on a sample batch, timing each candidate
+with HIP events on the run's stream. Every candidate must reproduce the
+reference cluster ids and seed flags bit for bit, or the tuner raises: the
+tuning may change speed only. The winner is cached as JSON, keyed by GPU
+architecture, CU count, clustering parameters and an occupancy bucket
+(log2 of hits per event), and is reused by later contexts with the same key.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import time
+
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "clue_mi355x_tuning.json")
+
+# Axes searched in this order; each axis keeps the best value found so far.
+def default_space(params):
+    dc = float(params["dc"])
+    dm = max(float(params["delta_c"]), float(params["delta_o"]))
+    base_t = max(dm, 2.0 * dc) * (1.0 + 1.0 / 128.0)
+    return [
+        ("density_quads", [1, 2]),
+        ("block", [(8, 8), (8, 4), (16, 8), (4, 4), (16, 16)]),
+        ("lds_cap", [1024, 512, 2048]),
+        ("tile_size", [base_t, base_t * 1.25, base_t * 1.5]),
+        ("nh_first_radius", [0.25 * dm, 0.375 * dm, 0.5 * dm, 0.0]),
+        ("threads_per_query", [1, 2, 4]),
+    ]
+
+
+def cache_key(params, n_hits, n_events, arch=None, n_cu=None):
+    import torch
+    if arch is None or n_cu is None:
+        prop = torch.cuda.get_device_properties(torch.cuda.current_device())
+        arch = arch or getattr(prop, "gcnArchName", "unknown").split(":")[0]
+        n_cu = n_cu or prop.multi_processor_count
+    per_event = max(1, n_hits // max(1, n_events))
+    bucket = int(round(math.log2(per_event)))
+    p = "_".join(f"{k}={float(params[k]):g}" for k in ("dc", "rho_c", "delta_c", "delta_o"))
+    extent = params.get("extent", params.get("bounds"))
+    return f"{arch}/cu{n_cu}/{p}/extent={extent}/layers={params.get('n_layers')}/hits2^{bucket}"
+
+
+def load_cached(key, path=DEFAULT_CACHE):
+    try:
+        with open(path) as f:
+            return json.load(f).get(key)
+    except (OSError, ValueError):
+        return None
+
+
+def store_cached(key, tuning, path=DEFAULT_CACHE):
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        data = {}
+        if os.path.exists(path):
+            with open(path) as f:
+                data = json.load(f)
+        data[key] = tuning
+        tmp = path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(data, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    except (OSError, ValueError):
+        pass
+
+
+def _apply(ctx, t):
+    bx, by = t["block"]
+    ctx.set_tuning(tile_size=t["tile_size"], threads_per_query=t["threads_per_query"], block_x=bx, block_y=by,
+                   lds_cap=t["lds_cap"], nh_first_radius=t["nh_first_radius"], density_quads=t["density_quads"])
+
+
+def autotune(ctx, batch, n_events, params, *, reps=3, space=None, stage_times=False, log=print):
+    """Tunes ``ctx`` on ``batch`` (dict of device tensors event, x, y, layer,
+    energy) and leaves the best tuning applied. Returns (best, table)."""
+    import torch
+    stream = torch.cuda.current_stream()
+    n = int(batch["x"].numel())
+    cid = torch.empty(n, dtype=torch.int32, device=batch["x"].device)
+    seed = torch.empty(n, dtype=torch.uint8, device=batch["x"].device)
+
+    def run():
+        ctx.run_batch(batch["event"], n_events, batch["x"], batch["y"], batch["layer"], batch["energy"], cid, seed)
+
+    cur = ctx.tuning()
+    best = dict(tile_size=cur["tile_size"], threads_per_query=cur["threads_per_query"],
+                block=(cur["block_x"], cur["block_y"]), lds_cap=cur["lds_cap"],
+                nh_first_radius=cur["nh_first_radius"], density_quads=cur["density_quads"])
+    run()
+    torch.cuda.synchronize()
+    ctx.status()
+    ref_cid, ref_seed = cid.clone(), seed.clone()
+    table = []
+
+    def measure(t):
+        try:
+            _apply(ctx, t)
+        except Exception as e:  # an impossible combination (e.g. region too large)
+            return None, str(e)
+        run()
+        torch.cuda.synchronize()
+        ctx.status()
+        if not (torch.equal(cid, ref_cid) and torch.equal(seed, ref_seed)):
+            raise RuntimeError(f"tuning {t} changed the clustering output")
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            run()
+        e1.record(stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        st = None
+        if stage_times:
+            ctx.enable_stage_timing(True)
+            run()
+            st = ctx.stage_times()
+            ctx.enable_stage_timing(False)
+        return ms, st
+
+    best_ms, st = measure(best)
+    table.append(dict(best, ms=best_ms, stages=st))
+    for axis, values in (space or default_space(params)):
+        for v in values:
+            t = dict(best)
+            t[axis] = v
+            if t == best:
+                continue
+            ms, st = measure(t)
+            table.append(dict(t, ms=ms, stages=st))
+            if log:
+                log(f"autotune {axis}={v}: {ms if ms is None else round(ms, 4)} ms")
+            if ms is not None and ms < best_ms:
+                best, best_ms = t, ms
+    _apply(ctx, best)
+    return dict(best, ms=best_ms), table
+
+
+def tuned_context_setup(ctx, batch, n_events, params, *, cache_path=DEFAULT_CACHE, reps=3, log=None):
+    """Applies a cached tuning for this workload, or tunes and caches one."""
+    key = cache_key(params, int(batch["x"].numel()), n_events)
+    t = load_cached(key, cache_path)
+    if t is not None:
+        t = dict(t)
+        t["block"] = tuple(t["block"])
+        _apply(ctx, t)
+        return t, "cache"
+    t0 = time.time()
+    best, _ = autotune(ctx, batch, n_events, params, reps=reps, log=log)
+    best = dict(best)
+    best["tuned_seconds"] = round(time.time() - t0, 1)
+    store_cached(key, best, cache_path)
+    return best, "tuned"

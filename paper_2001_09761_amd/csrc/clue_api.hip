@@ -23,6 +23,7 @@ struct clue_ctx {
   float tile = 0.0f;
   int tpq = 1, bx = 8, by = 8, lds_cap = kDefaultLdsCap;
   float r1 = -1.0f;  // nearest-higher first radius; negative: default d_m / 4
+  int quads = 1;      // density strategy (1 quads, 2 per-query merge)
   LaunchCfg cfg{};
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -61,8 +62,8 @@ static inline bool finite(float v) { return std::isfinite(v); }
 // ---------------------------------------------------------------------------
 // Geometry: tile size, halo and window bounds.
 // ---------------------------------------------------------------------------
-static int plan_geom(const clue_params& p, float tile, int tpq, int bx, int by, int lds_cap, float r1, Geom& g,
-                     std::string& msg) {
+static int plan_geom(const clue_params& p, float tile, int tpq, int bx, int by, int lds_cap, float r1, int quads,
+                     Geom& g, std::string& msg) {
   if (!finite(p.dc) || !(p.dc > 0.0f) || !finite(p.rho_c) || !finite(p.delta_c) || !finite(p.delta_o) ||
       p.delta_c < 0.0f || p.delta_o < 0.0f) {
     msg = "invalid clustering parameters (need finite dc > 0, rho_c, delta_c >= 0, delta_o >= 0)";
@@ -119,6 +120,7 @@ static int plan_geom(const clue_params& p, float tile, int tpq, int bx, int by, 
   g.win_dc = (float)((double)p.dc * (1.0 + 1.0 / 1024.0));
   g.win_dm = (float)((double)dm * (1.0 + 1.0 / 1024.0));
   g.flags = p.flags;
+  g.density_quads = quads == 2 ? 0 : 1;
   // First nearest-higher pass: radius r1 (default d_m / 4); off when r1 <= 0
   // or r1 >= d_m.
   const float r1v = r1 < 0.0f ? 0.25f * dm : r1;
@@ -322,7 +324,7 @@ int clue_footprint_bytes(const clue_params* p, int64_t max_hits, int32_t max_eve
   Geom g{};
   std::string msg;
   const int tpq = p->threads_per_query > 0 ? p->threads_per_query : 1;
-  int rc = plan_geom(*p, p->tile_size, tpq, 8, 8, kDefaultLdsCap, -1.0f, g, msg);
+  int rc = plan_geom(*p, p->tile_size, tpq, 8, 8, kDefaultLdsCap, -1.0f, 1, g, msg);
   if (rc != CLUE_OK) return rc;
   ArenaPlan P;
   if (!plan_arena(g, p->flags, max_hits, max_events, P)) return CLUE_ERR_CAPACITY;
@@ -345,7 +347,7 @@ int clue_create(clue_ctx** out, const clue_params* p, int hip_device, int64_t ma
   c->tpq = p->threads_per_query > 0 ? p->threads_per_query : 1;
   c->tile = p->tile_size;
   std::string msg;
-  int rc = plan_geom(c->params, c->tile, c->tpq, c->bx, c->by, c->lds_cap, c->r1, c->g, msg);
+  int rc = plan_geom(c->params, c->tile, c->tpq, c->bx, c->by, c->lds_cap, c->r1, c->quads, c->g, msg);
   if (rc != CLUE_OK) {
     set_err(nullptr, rc, msg);
     delete c;
@@ -543,7 +545,8 @@ int clue_set_tuning(clue_ctx* c, const clue_tuning* t) {
   const int bx = t->block_x > 0 ? t->block_x : c->bx, by = t->block_y > 0 ? t->block_y : c->by;
   const int cap = t->lds_cap > 0 ? t->lds_cap : c->lds_cap;
   const float r1 = t->nh_first_radius >= 0.0f ? t->nh_first_radius : c->r1;
-  int rc = plan_geom(c->params, tile, tpq, bx, by, cap, r1, g, msg);
+  const int quads = t->density_quads > 0 ? t->density_quads : c->quads;
+  int rc = plan_geom(c->params, tile, tpq, bx, by, cap, r1, quads, g, msg);
   if (rc != CLUE_OK) return set_err(c, rc, msg);
   HIP_TRY(c, hipSetDevice(c->device));
   HIP_TRY(c, hipDeviceSynchronize());
@@ -566,6 +569,7 @@ int clue_set_tuning(clue_ctx* c, const clue_tuning* t) {
   c->by = by;
   c->lds_cap = cap;
   c->r1 = r1;
+  c->quads = quads;
   return CLUE_OK;
 }
 
@@ -578,6 +582,7 @@ int clue_get_tuning(const clue_ctx* c, clue_tuning* t, int32_t* halo) {
     t->block_y = c->g.by;
     t->lds_cap = c->g.lds_cap;
     t->nh_first_radius = c->g.nh_phase1 ? std::sqrt(c->g.r1sq) : 0.0f;
+    t->density_quads = c->g.density_quads ? 1 : 2;
   }
   if (halo) *halo = c->g.halo;
   return CLUE_OK;

@@ -723,7 +723,7 @@ __device__ void density_staged(const Geom& g, const Arena& a, const Region& R, R
   const int qy0 = max(R.cy0 - 1, 0), qy1 = min(R.cy0 + R.ch - 1, R.rh - 1);
   const int qw = qx1 - qx0 + 1;
   const int nquad = qw * (qy1 - qy0 + 1);
-  bool use_quads = MAXL == 2 && nquad <= kMaxQuads;
+  bool use_quads = MAXL == 2 && g.density_quads && nquad <= kMaxQuads;
   if (use_quads) {
     if (threadIdx.x < 64) {
       // quad sizes -> offsets, 64 quads per wave step
