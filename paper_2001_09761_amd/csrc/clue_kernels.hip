@@ -589,8 +589,17 @@ __device__ __forceinline__ float density_two_pass(const float4* __restrict__ rec
     big |= len > 64;
     const float4* base = rec + lo[k];
     const int n0 = min(len, 32);
-#pragma unroll 4
-    for (int c = 0; c < n0; ++c) {
+    int c = 0;
+    for (; c + 3 < n0; c += 4) {
+      const float2 q0 = *reinterpret_cast<const float2*>(base + c);
+      const float2 q1 = *reinterpret_cast<const float2*>(base + c + 1);
+      const float2 q2 = *reinterpret_cast<const float2*>(base + c + 2);
+      const float2 q3 = *reinterpret_cast<const float2*>(base + c + 3);
+      const unsigned m4 = (dist2(xi, yi, q0.x, q0.y) < dc2 ? 1u : 0u) | (dist2(xi, yi, q1.x, q1.y) < dc2 ? 2u : 0u) |
+                          (dist2(xi, yi, q2.x, q2.y) < dc2 ? 4u : 0u) | (dist2(xi, yi, q3.x, q3.y) < dc2 ? 8u : 0u);
+      mlo[k] |= m4 << c;
+    }
+    for (; c < n0; ++c) {
       const float2 q = *reinterpret_cast<const float2*>(base + c);
       mlo[k] |= (dist2(xi, yi, q.x, q.y) < dc2 ? 1u : 0u) << c;
     }
@@ -794,11 +803,25 @@ __device__ void density_staged(const Geom& g, const Arena& a, const Region& R, R
     float rho = 0.0f;
     if (ok && use_quads) {
       const int qq = (ty0 - qy0) * qw + (tx0 - qx0);
-      const int c0 = L.qoff[qq], c1 = L.qoff[qq + 1];
-#pragma unroll 4
-      for (int c = c0; c < c1; ++c) {
+      const int c1 = L.qoff[qq + 1];
+      int c = L.qoff[qq];
+      // loads batched four at a time; additions stay in ascending index order
+      for (; c + 3 < c1; c += 4) {
+        const int i0 = qidx[c], i1 = qidx[c + 1], i2 = qidx[c + 2], i3 = qidx[c + 3];
+        const float4 r0 = rec[i0], r1 = rec[i1], r2 = rec[i2], r3 = rec[i3];
+        const float a0 = __fadd_rn(rho, r0.z);
+        rho = dist2(xi, yi, r0.x, r0.y) < g.dc2 ? a0 : rho;
+        const float a1 = __fadd_rn(rho, r1.z);
+        rho = dist2(xi, yi, r1.x, r1.y) < g.dc2 ? a1 : rho;
+        const float a2 = __fadd_rn(rho, r2.z);
+        rho = dist2(xi, yi, r2.x, r2.y) < g.dc2 ? a2 : rho;
+        const float a3 = __fadd_rn(rho, r3.z);
+        rho = dist2(xi, yi, r3.x, r3.y) < g.dc2 ? a3 : rho;
+      }
+      for (; c < c1; ++c) {
         const float4 r = rec[qidx[c]];
-        if (dist2(xi, yi, r.x, r.y) < g.dc2) rho = __fadd_rn(rho, r.z);
+        const float a = __fadd_rn(rho, r.z);
+        rho = dist2(xi, yi, r.x, r.y) < g.dc2 ? a : rho;
       }
     } else if (ok) {
       int lo[MAXL * MAXL], hi[MAXL * MAXL];
@@ -910,10 +933,9 @@ __device__ __forceinline__ void nh_consider(NhBest& b, float d2, unsigned ordj, 
                                             unsigned hi, float thr) {
   const bool higher = STRICT ? ordj > ordi : key64(ordj, hj) > key64(ordi, hi);
   const unsigned long long ck = key64(__float_as_uint(d2), hj);
-  if (d2 < thr && higher && ck < b.k) {
-    b.k = ck;
-    b.p = pq;
-  }
+  const bool take = (d2 < thr) & higher & (ck < b.k);  // branch-free select
+  b.k = take ? ck : b.k;
+  b.p = take ? pq : b.p;
 }
 
 __device__ __forceinline__ void nh_reduce(NhBest& b, int tpq) {
@@ -955,8 +977,20 @@ __device__ __forceinline__ void nh_scan_staged(const float4* __restrict__ rec, c
   for (int ty = ty0; ty <= ty1; ++ty) {
     const int q0 = L.ts[ty * per_row + tx0];
     const int q1 = L.ts[ty * per_row + tx1 + 1];
-#pragma unroll 4
-    for (int c = q0 + sub; c < q1; c += step) {
+    int c = q0 + sub;
+    // four independent LDS loads in flight per step
+    for (; c + 3 * step < q1; c += 4 * step) {
+      const float4 r0 = rec[c], r1 = rec[c + step], r2 = rec[c + 2 * step], r3 = rec[c + 3 * step];
+      nh_consider<STRICT>(b, dist2(xi, yi, r0.x, r0.y), __float_as_uint(r0.z), __float_as_uint(r0.w), c, ordi, hi,
+                          thr);
+      nh_consider<STRICT>(b, dist2(xi, yi, r1.x, r1.y), __float_as_uint(r1.z), __float_as_uint(r1.w), c + step,
+                          ordi, hi, thr);
+      nh_consider<STRICT>(b, dist2(xi, yi, r2.x, r2.y), __float_as_uint(r2.z), __float_as_uint(r2.w),
+                          c + 2 * step, ordi, hi, thr);
+      nh_consider<STRICT>(b, dist2(xi, yi, r3.x, r3.y), __float_as_uint(r3.z), __float_as_uint(r3.w),
+                          c + 3 * step, ordi, hi, thr);
+    }
+    for (; c < q1; c += step) {
       const float4 r = rec[c];
       nh_consider<STRICT>(b, dist2(xi, yi, r.x, r.y), __float_as_uint(r.z), __float_as_uint(r.w), c, ordi, hi, thr);
     }
