@@ -501,12 +501,34 @@ __device__ __forceinline__ void core_query(const RegionLds& L, const Region& R, 
 
 __device__ __forceinline__ int slot_of(const RegionLds& L, int row, int p) { return L.row_gs[row] + (p - L.row_lo[row]); }
 
-// Pops the next work item from a queue head; uniform across the workgroup.
-__device__ __forceinline__ int pop_item(int* head, int* s_item) {
-  __syncthreads();
-  if (threadIdx.x == 0) *s_item = atomicAdd(head, 1);
-  __syncthreads();
-  return *s_item;
+// Work-item scheduling. Plain launches have one workgroup per item; block b
+// runs on XCD b % 8, so items are remapped to give each XCD a contiguous run
+// of spatially adjacent blocks (its own L2 then holds their shared halos).
+// Persistent launches pop chunks of adjacent items from a device queue head
+// (one atomic per chunk keeps the head uncontended).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_item(int b, int n) {
+  const int q = n / kXcds, r = n - q * kXcds;
+  const int x = b % kXcds, k = b / kXcds;
+  return x * q + min(x, r) + k;
+}
+
+template <bool G, class F>
+__device__ __forceinline__ void for_each_item(int n_items, int* head, int* s_item, F&& body) {
+  if constexpr (!G) {
+    if ((int)blockIdx.x < n_items) body(xcd_item((int)blockIdx.x, n_items));
+  } else {
+    const int chunk = max(1, min(16, n_items / ((int)gridDim.x * 4)));
+    for (;;) {
+      __syncthreads();
+      if (threadIdx.x == 0) *s_item = atomicAdd(head, chunk);
+      __syncthreads();
+      const int base = *s_item;
+      if (base >= n_items) break;
+      const int end = min(base + chunk, n_items);
+      for (int it = base; it < end; ++it) body(it);
+    }
+  }
 }
 
 // Query window [v - w', v + w'] in tile coordinates (w' from window_half).
@@ -874,18 +896,16 @@ __global__ __launch_bounds__(kWG) void k_density(DescArg<G> dg, Geom g, Arena a)
   unsigned short* qidx = stile + g.lds_cap;
   const int n_items = d.n_events * g.L * g.bpu;
   const bool keep = g.flags & 2u;
-  for (;;) {
-    const int item = pop_item(&a.counters[C_QUEUE_RHO], &s_item);
-    if (item >= n_items) break;
+  for_each_item<G>(n_items, &a.counters[C_QUEUE_RHO], &s_item, [&](int item) {
     int unit, tx0, ty0, tx1, ty1;
     item_block(g, item, unit, tx0, ty0, tx1, ty1);
     Region R;
     make_region(g, unit, tx0, ty0, tx1, ty1, R);
     region_setup(g, a, R, L);
-    if (L.core_lo[R.ch] == 0) continue;
+    if (L.core_lo[R.ch] == 0) return;
     if (R.total <= g.lds_cap) {
       density_staged<MAXL>(g, a, R, L, rec, stmp, stile, qidx, keep);
-      continue;
+      return;
     }
     for (int ty = ty0; ty <= ty1; ++ty)
       for (int tx = tx0; tx <= tx1; ++tx) {
@@ -897,7 +917,7 @@ __global__ __launch_bounds__(kWG) void k_density(DescArg<G> dg, Geom g, Arena a)
         else
           density_global_region(g, a, R, L, keep);
       }
-  }
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -1150,14 +1170,12 @@ __global__ __launch_bounds__(kWG) void k_nearest_higher(DescArg<G> dg, Geom g, A
   int* queue = reinterpret_cast<int*>(rec + g.lds_cap);
   const int n_items = d.n_events * g.L * g.bpu;
   const bool strict = g.flags & 4u;
-  for (;;) {
-    const int item = pop_item(&a.counters[C_QUEUE_NH], &s_item);
-    if (item >= n_items) break;
+  for_each_item<G>(n_items, &a.counters[C_QUEUE_NH], &s_item, [&](int item) {
     if (strict)
       nh_item<true>(g, a, d, item, L, rec, queue, &s_qn);
     else
       nh_item<false>(g, a, d, item, L, rec, queue, &s_qn);
-  }
+  });
 }
 
 // ---------------------------------------------------------------------------
