@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 
@@ -257,6 +258,10 @@ static void compute_cfg(clue_ctx* c) {
   c->cfg.persist_blocks_stream = c->n_cu * std::min(occupancy_blocks_per_cu(0, 0), 8);
   c->cfg.persist_blocks_rho = c->n_cu * occupancy_blocks_per_cu(1, lds);
   c->cfg.persist_blocks_nh = c->n_cu * occupancy_blocks_per_cu(3, lds_bytes_nh(c->g.lds_cap));
+  if (std::getenv("CLUE_VERBOSE"))
+    std::fprintf(stderr, "clue: persistent grids stream=%d rho=%d nh=%d scan=%d (cu=%d, lds rho=%d nh=%d)\n",
+                 c->cfg.persist_blocks_stream, c->cfg.persist_blocks_rho, c->cfg.persist_blocks_nh,
+                 c->cfg.persist_blocks_scan, c->n_cu, lds, lds_bytes_nh(c->g.lds_cap));
   c->cfg.persist_blocks_scan = c->n_cu * std::min(occupancy_blocks_per_cu(2, 0), 4);
 }
 

@@ -501,29 +501,33 @@ __device__ __forceinline__ void core_query(const RegionLds& L, const Region& R, 
 
 __device__ __forceinline__ int slot_of(const RegionLds& L, int row, int p) { return L.row_gs[row] + (p - L.row_lo[row]); }
 
-// Work-item scheduling, XCD-aware. Workgroup b runs on XCD b % 8, and each
-// XCD has its own L2, so every XCD gets one contiguous run of items
-// (spatially adjacent tile blocks of the same layers) and its workgroups
-// interleave over that run: concurrently processed items stay adjacent and
-// share their halo tiles in that XCD's L2. Plain launches have one workgroup
-// per item; persistent launches stride over their XCD's run. No atomics.
+// Work-item scheduling. Plain launches have one workgroup per item;
+// workgroup b runs on XCD b % 8 and each XCD has its own L2, so items are
+// remapped to give every XCD one contiguous run of spatially adjacent tile
+// blocks. Persistent launches pop items one at a time from a device queue
+// head, in order: the items in flight across the GPU stay adjacent (their
+// halos shared in cache), and a workgroup that starts late or meets a dense
+// item never holds up the rest.
 constexpr int kXcds = 8;
-__device__ __forceinline__ void xcd_range(int n, int x, int& lo, int& cnt) {
+__device__ __forceinline__ int xcd_item(int b, int n) {
   const int q = n / kXcds, r = n - q * kXcds;
-  lo = x * q + min(x, r);
-  cnt = q + (x < r ? 1 : 0);
+  const int x = b % kXcds, k = b / kXcds;
+  return x * q + min(x, r) + k;
 }
 
 template <bool G, class F>
-__device__ __forceinline__ void for_each_item(int n_items, F&& body) {
-  const int x = (int)blockIdx.x % kXcds, j = (int)blockIdx.x / kXcds;
-  int lo, cnt;
-  xcd_range(n_items, x, lo, cnt);
+__device__ __forceinline__ void for_each_item(int n_items, int* head, int* s_item, F&& body) {
   if constexpr (!G) {
-    if (j < cnt) body(lo + j);
+    if ((int)blockIdx.x < n_items) body(xcd_item((int)blockIdx.x, n_items));
   } else {
-    const int per_xcd = ((int)gridDim.x - x + kXcds - 1) / kXcds;  // workgroups on this XCD
-    for (int k = j; k < cnt; k += per_xcd) body(lo + k);
+    for (;;) {
+      __syncthreads();
+      if (threadIdx.x == 0) *s_item = atomicAdd(head, 1);
+      __syncthreads();
+      const int item = *s_item;
+      if (item >= n_items) break;
+      body(item);
+    }
   }
 }
 
@@ -885,13 +889,14 @@ __global__ __launch_bounds__(kWG) void k_density(DescArg<G> dg, Geom g, Arena a)
   const RunDesc d = dg.get();
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ RegionLds L;
+  __shared__ int s_item;
   float4* rec = reinterpret_cast<float4*>(smem);
   int* stmp = reinterpret_cast<int*>(rec + g.lds_cap);
   unsigned short* stile = reinterpret_cast<unsigned short*>(stmp + g.lds_cap);
   unsigned short* qidx = stile + g.lds_cap;
   const int n_items = d.n_events * g.L * g.bpu;
   const bool keep = g.flags & 2u;
-  for_each_item<G>(n_items, [&](int item) {
+  for_each_item<G>(n_items, &a.counters[C_QUEUE_RHO], &s_item, [&](int item) {
     int unit, tx0, ty0, tx1, ty1;
     item_block(g, item, unit, tx0, ty0, tx1, ty1);
     Region R;
@@ -1160,11 +1165,12 @@ __global__ __launch_bounds__(kWG) void k_nearest_higher(DescArg<G> dg, Geom g, A
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ RegionLds L;
   __shared__ int s_qn;
+  __shared__ int s_item;
   float4* rec = reinterpret_cast<float4*>(smem);
   int* queue = reinterpret_cast<int*>(rec + g.lds_cap);
   const int n_items = d.n_events * g.L * g.bpu;
   const bool strict = g.flags & 4u;
-  for_each_item<G>(n_items, [&](int item) {
+  for_each_item<G>(n_items, &a.counters[C_QUEUE_NH], &s_item, [&](int item) {
     if (strict)
       nh_item<true>(g, a, d, item, L, rec, queue, &s_qn);
     else
