@@ -16,13 +16,17 @@ constexpr int kMaxQuads = 289;        // (block + 1)^2 quads for blocks up to 16
 constexpr int kDefaultLdsCap = 1024;   // staged hits per workgroup (fast path)
 constexpr int kMaxLdsCap = 2048;
 
-// Counters in device memory, cleared at the start of every run.
+// Counters in device memory, cleared at the start of every run. Each sits on
+// its own 256-byte line so that atomics on different counters do not
+// contend; the tile-block stages have one queue head per XCD.
+constexpr int kCounterStride = 64;  // ints
+constexpr int kQueues = 8;          // one per XCD
 enum Counter {
-  C_TICKET_TILES = 0,  // chunk tickets of the tile-count scan
-  C_TICKET_SEEDS = 1,  // chunk tickets of the seed / follower scan
-  C_QUEUE_RHO = 2,     // work-queue head of the density stage
-  C_QUEUE_NH = 3,      // work-queue head of the nearest-higher stage
-  C_COUNT = 8
+  C_TICKET_TILES = 0,                           // chunk tickets of the tile-count scan
+  C_TICKET_SEEDS = 1 * kCounterStride,          // chunk tickets of the seed / follower scan
+  C_QUEUE_RHO = 2 * kCounterStride,             // kQueues heads for the density stage
+  C_QUEUE_NH = (2 + kQueues) * kCounterStride,  // kQueues heads for the nearest-higher stage
+  C_COUNT = (2 + 2 * kQueues) * kCounterStride
 };
 
 // Device error word bits (read and cleared by clue_status).

@@ -121,7 +121,7 @@ __global__ __launch_bounds__(kWG) void k_clear(DescArg<G> dg, Geom g, Arena a) {
   const int64_t nchunk_s = (n1 + kScanChunk - 1) / kScanChunk;
   for (int64_t i = i0; i < nchunk_t && i < a.cap_chunks; i += stride) a.scan_status[i] = 0ull;
   for (int64_t i = i0; i < nchunk_s && i < a.cap_chunks; i += stride) a.scan_status[a.cap_chunks + i] = 0ull;
-  if (i0 < C_COUNT) a.counters[i0] = 0;
+  for (int64_t i = i0; i < C_COUNT; i += stride) a.counters[i] = 0;
   for (int64_t i = i0; i <= d.n_events; i += stride) a.ev_start[i] = 0;
 }
 
@@ -501,32 +501,43 @@ __device__ __forceinline__ void core_query(const RegionLds& L, const Region& R, 
 
 __device__ __forceinline__ int slot_of(const RegionLds& L, int row, int p) { return L.row_gs[row] + (p - L.row_lo[row]); }
 
-// Work-item scheduling. Plain launches have one workgroup per item;
-// workgroup b runs on XCD b % 8 and each XCD has its own L2, so items are
-// remapped to give every XCD one contiguous run of spatially adjacent tile
-// blocks. Persistent launches pop items one at a time from a device queue
-// head, in order: the items in flight across the GPU stay adjacent (their
-// halos shared in cache), and a workgroup that starts late or meets a dense
-// item never holds up the rest.
-constexpr int kXcds = 8;
-__device__ __forceinline__ int xcd_item(int b, int n) {
-  const int q = n / kXcds, r = n - q * kXcds;
-  const int x = b % kXcds, k = b / kXcds;
-  return x * q + min(x, r) + k;
+// Work-item scheduling. Items are (event, layer, tile block) triples in
+// row-major block order, so consecutive items are spatially adjacent and
+// share halo tiles. Plain launches take item = workgroup id: the dispatcher
+// issues workgroups in order, so the items in flight stay adjacent.
+// Persistent launches split the items into one contiguous run per XCD (each
+// XCD has its own L2) and pop them from that XCD's queue head; an XCD whose
+// run is exhausted steals from the others. The XCD comes from the hardware
+// XCC_ID register.
+__device__ __forceinline__ int xcc_id() {
+  // s_getreg_b32 hwreg(HW_REG_XCC_ID = 20, offset 0, 4 bits)
+  return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & (kQueues - 1);
+}
+
+__device__ __forceinline__ void queue_range(int n, int x, int& lo, int& cnt) {
+  const int q = n / kQueues, r = n - q * kQueues;
+  lo = x * q + min(x, r);
+  cnt = q + (x < r ? 1 : 0);
 }
 
 template <bool G, class F>
-__device__ __forceinline__ void for_each_item(int n_items, int* head, int* s_item, F&& body) {
+__device__ __forceinline__ void for_each_item(int n_items, int* heads, int* s_item, F&& body) {
   if constexpr (!G) {
-    if ((int)blockIdx.x < n_items) body(xcd_item((int)blockIdx.x, n_items));
+    if ((int)blockIdx.x < n_items) body((int)blockIdx.x);
   } else {
-    for (;;) {
-      __syncthreads();
-      if (threadIdx.x == 0) *s_item = atomicAdd(head, 1);
-      __syncthreads();
-      const int item = *s_item;
-      if (item >= n_items) break;
-      body(item);
+    const int home = xcc_id();
+    for (int v = 0; v < kQueues; ++v) {  // own queue first, then steal
+      const int x = (home + v) & (kQueues - 1);
+      int lo, cnt;
+      queue_range(n_items, x, lo, cnt);
+      for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) *s_item = atomicAdd(&heads[x * kCounterStride], 1);
+        __syncthreads();
+        const int k = *s_item;
+        if (k >= cnt) break;
+        body(lo + k);
+      }
     }
   }
 }
