@@ -444,7 +444,7 @@ __device__ __forceinline__ void make_region(const Geom& g, int unit, int tx0, in
 
 // Loads the region's tile offsets and builds the LDS layout. Starts and ends
 // with a barrier; R.total and the core counts are then valid everywhere.
-__device__ void region_setup(const Geom& g, const Arena& a, Region& R, RegionLds& L) {
+__device__ __forceinline__ void region_setup(const Geom& g, const Arena& a, Region& R, RegionLds& L) {
   __syncthreads();
   const int64_t ubase = (int64_t)R.unit * g.tpl;
   const int per_row = R.rw + 1;
@@ -520,25 +520,30 @@ __device__ __forceinline__ void queue_range(int n, int x, int& lo, int& cnt) {
   cnt = q + (x < r ? 1 : 0);
 }
 
-template <bool G, class F>
-__device__ __forceinline__ void for_each_item(int n_items, int* heads, int* s_item, F&& body) {
+struct ItemSched {
+  int v;     // queues visited so far (persistent) / item taken (plain)
+  int home;  // this workgroup's XCD
+};
+
+// Next work item, or -1 when none is left; uniform across the workgroup.
+template <bool G>
+__device__ __forceinline__ int next_item(ItemSched& st, int n_items, int* heads, int* s_item) {
   if constexpr (!G) {
-    if ((int)blockIdx.x < n_items) body((int)blockIdx.x);
+    if (st.v++ > 0) return -1;
+    return (int)blockIdx.x < n_items ? (int)blockIdx.x : -1;
   } else {
-    const int home = xcc_id();
-    for (int v = 0; v < kQueues; ++v) {  // own queue first, then steal
-      const int x = (home + v) & (kQueues - 1);
+    while (st.v < kQueues) {  // own XCD's queue first, then steal
+      const int x = (st.home + st.v) & (kQueues - 1);
       int lo, cnt;
       queue_range(n_items, x, lo, cnt);
-      for (;;) {
-        __syncthreads();
-        if (threadIdx.x == 0) *s_item = atomicAdd(&heads[x * kCounterStride], 1);
-        __syncthreads();
-        const int k = *s_item;
-        if (k >= cnt) break;
-        body(lo + k);
-      }
+      __syncthreads();
+      if (threadIdx.x == 0) *s_item = atomicAdd(&heads[x * kCounterStride], 1);
+      __syncthreads();
+      const int k = *s_item;
+      if (k < cnt) return lo + k;
+      ++st.v;
     }
+    return -1;
   }
 }
 
@@ -564,7 +569,7 @@ __device__ __forceinline__ Window query_window(const Geom& g, float w, float xi,
 // Records: (x, y, E, hit index as bits).
 // ---------------------------------------------------------------------------
 template <int MAXL>
-__device__ float density_merge_full(const float4* __restrict__ rec, const int* lo, const int* hi, float xi, float yi,
+__device__ __forceinline__ float density_merge_full(const float4* __restrict__ rec, const int* lo, const int* hi, float xi, float yi,
                                     float dc2) {
   constexpr int K = MAXL * MAXL;
   int cur[K], head[K];
@@ -699,7 +704,7 @@ __device__ __forceinline__ float density_two_pass(const float4* __restrict__ rec
 // Global-memory density: tile lists in arrival order; the neighbours are
 // visited in ascending index by repeatedly taking the smallest index above
 // the previous one.
-__device__ float density_global(const Geom& g, const Arena& a, int64_t ubase, float xi, float yi) {
+__device__ __forceinline__ float density_global(const Geom& g, const Arena& a, int64_t ubase, float xi, float yi) {
   const Window W = query_window(g, g.win_dc, xi, yi);
   float acc = 0.0f;
   int last = -1;
@@ -732,7 +737,7 @@ __device__ float density_global(const Geom& g, const Arena& a, int64_t ubase, fl
 // ascending hit index. Otherwise (or if the quads do not fit) a query merges
 // its window's tile lists itself.
 template <int MAXL>
-__device__ void density_staged(const Geom& g, const Arena& a, const Region& R, RegionLds& L, float4* rec, int* stmp,
+__device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, const Region& R, RegionLds& L, float4* rec, int* stmp,
                                unsigned short* stile, unsigned short* qidx, bool keep) {
   const int per_row = R.rw + 1;
   const int64_t ubase = (int64_t)R.unit * g.tpl;
@@ -882,7 +887,7 @@ __device__ void density_staged(const Geom& g, const Arena& a, const Region& R, R
   }
 }
 
-__device__ void density_global_region(const Geom& g, const Arena& a, const Region& R, const RegionLds& L, bool keep) {
+__device__ __forceinline__ void density_global_region(const Geom& g, const Arena& a, const Region& R, const RegionLds& L, bool keep) {
   const int64_t ubase = (int64_t)R.unit * g.tpl;
   const int nq = L.core_lo[R.ch];
   for (int q = threadIdx.x; q < nq; q += kWG) {
@@ -907,16 +912,17 @@ __global__ __launch_bounds__(kWG) void k_density(DescArg<G> dg, Geom g, Arena a)
   unsigned short* qidx = stile + g.lds_cap;
   const int n_items = d.n_events * g.L * g.bpu;
   const bool keep = g.flags & 2u;
-  for_each_item<G>(n_items, &a.counters[C_QUEUE_RHO], &s_item, [&](int item) {
+  ItemSched st{0, G ? xcc_id() : 0};
+  for (int item; (item = next_item<G>(st, n_items, &a.counters[C_QUEUE_RHO], &s_item)) >= 0;) {
     int unit, tx0, ty0, tx1, ty1;
     item_block(g, item, unit, tx0, ty0, tx1, ty1);
     Region R;
     make_region(g, unit, tx0, ty0, tx1, ty1, R);
     region_setup(g, a, R, L);
-    if (L.core_lo[R.ch] == 0) return;
+    if (L.core_lo[R.ch] == 0) continue;
     if (R.total <= g.lds_cap) {
       density_staged<MAXL>(g, a, R, L, rec, stmp, stile, qidx, keep);
-      return;
+      continue;
     }
     for (int ty = ty0; ty <= ty1; ++ty)
       for (int tx = tx0; tx <= tx1; ++tx) {
@@ -928,7 +934,7 @@ __global__ __launch_bounds__(kWG) void k_density(DescArg<G> dg, Geom g, Arena a)
         else
           density_global_region(g, a, R, L, keep);
       }
-  });
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1029,7 +1035,7 @@ __device__ __forceinline__ void nh_scan_staged(const float4* __restrict__ rec, c
 }
 
 template <bool STRICT>
-__device__ void nh_global_scan(const Geom& g, const Arena& a, int64_t ubase, const Window& W, int sub, int step,
+__device__ __forceinline__ void nh_global_scan(const Geom& g, const Arena& a, int64_t ubase, const Window& W, int sub, int step,
                                float xi, float yi, unsigned ordi, unsigned hi, NhBest& b) {
   for (int ty = W.y0; ty <= W.y1; ++ty) {
     const int64_t t = ubase + (int64_t)ty * g.nx;
@@ -1041,7 +1047,7 @@ __device__ void nh_global_scan(const Geom& g, const Arena& a, int64_t ubase, con
 }
 
 template <bool STRICT>
-__device__ void nh_staged(const Geom& g, const Arena& a, const RunDesc& d, const Region& R, const RegionLds& L,
+__device__ __forceinline__ void nh_staged(const Geom& g, const Arena& a, const RunDesc& d, const Region& R, const RegionLds& L,
                           float4* rec, int* queue, int* s_qn, int ev_first) {
   const int per_row = R.rw + 1;
   const int64_t ubase = (int64_t)R.unit * g.tpl;
@@ -1114,7 +1120,7 @@ __device__ void nh_staged(const Geom& g, const Arena& a, const RunDesc& d, const
 }
 
 template <bool STRICT>
-__device__ void nh_global_region(const Geom& g, const Arena& a, const RunDesc& d, const Region& R,
+__device__ __forceinline__ void nh_global_region(const Geom& g, const Arena& a, const RunDesc& d, const Region& R,
                                  const RegionLds& L, int ev_first) {
   const int64_t ubase = (int64_t)R.unit * g.tpl;
   const int nq = L.core_lo[R.ch];
@@ -1145,7 +1151,7 @@ __device__ void nh_global_region(const Geom& g, const Arena& a, const RunDesc& d
 }
 
 template <bool STRICT>
-__device__ void nh_item(const Geom& g, const Arena& a, const RunDesc& d, int item, RegionLds& L, float4* rec,
+__device__ __forceinline__ void nh_item(const Geom& g, const Arena& a, const RunDesc& d, int item, RegionLds& L, float4* rec,
                         int* queue, int* s_qn) {
   int unit, tx0, ty0, tx1, ty1;
   item_block(g, item, unit, tx0, ty0, tx1, ty1);
@@ -1170,7 +1176,7 @@ __device__ void nh_item(const Geom& g, const Arena& a, const RunDesc& d, int ite
     }
 }
 
-template <bool G>
+template <bool G, bool STRICT>
 __global__ __launch_bounds__(kWG) void k_nearest_higher(DescArg<G> dg, Geom g, Arena a) {
   const RunDesc d = dg.get();
   extern __shared__ __align__(16) unsigned char smem[];
@@ -1180,13 +1186,9 @@ __global__ __launch_bounds__(kWG) void k_nearest_higher(DescArg<G> dg, Geom g, A
   float4* rec = reinterpret_cast<float4*>(smem);
   int* queue = reinterpret_cast<int*>(rec + g.lds_cap);
   const int n_items = d.n_events * g.L * g.bpu;
-  const bool strict = g.flags & 4u;
-  for_each_item<G>(n_items, &a.counters[C_QUEUE_NH], &s_item, [&](int item) {
-    if (strict)
-      nh_item<true>(g, a, d, item, L, rec, queue, &s_qn);
-    else
-      nh_item<false>(g, a, d, item, L, rec, queue, &s_qn);
-  });
+  ItemSched st{0, G ? xcc_id() : 0};
+  for (int item; (item = next_item<G>(st, n_items, &a.counters[C_QUEUE_NH], &s_item)) >= 0;)
+    nh_item<STRICT>(g, a, d, item, L, rec, queue, &s_qn);
 }
 
 // ---------------------------------------------------------------------------
@@ -1315,7 +1317,10 @@ static hipError_t launch_all(const Geom& g, const Arena& a, DescArg<G> dg, const
   else
     k_density<G, 3><<<g_rho, kWG, lds, s>>>(dg, g, a);
   mark();
-  k_nearest_higher<G><<<g_nh, kWG, lds_bytes_nh(g.lds_cap), s>>>(dg, g, a);
+  if (g.flags & 4u)
+    k_nearest_higher<G, true><<<g_nh, kWG, lds_bytes_nh(g.lds_cap), s>>>(dg, g, a);
+  else
+    k_nearest_higher<G, false><<<g_nh, kWG, lds_bytes_nh(g.lds_cap), s>>>(dg, g, a);
   mark();
   if (fol)
     k_scan<G, SCAN_SEEDS_FOLLOW><<<g_scan_s, kWG, 0, s>>>(dg, g, a);
@@ -1357,7 +1362,7 @@ int occupancy_blocks_per_cu(int which, int lds_bytes) {
     case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_hist<true>, kWG, 0); break;
     case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_density<true, 2>, kWG, lds_bytes); break;
     case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_scan<true, SCAN_SEEDS_FOLLOW>, kWG, 0); break;
-    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_nearest_higher<true>, kWG, lds_bytes); break;
+    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_nearest_higher<true, false>, kWG, lds_bytes); break;
     default: break;
   }
   if (e != hipSuccess || nb < 1) nb = 1;
