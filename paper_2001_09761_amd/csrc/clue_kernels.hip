@@ -737,8 +737,8 @@ __device__ __forceinline__ float density_global(const Geom& g, const Arena& a, i
 // ascending hit index. Otherwise (or if the quads do not fit) a query merges
 // its window's tile lists itself.
 template <int MAXL>
-__device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, const Region& R, RegionLds& L, float4* rec,
-                                               int* stmp, unsigned short* qidx, bool keep) {
+__device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, const Region& R, RegionLds& L, float4* rec, int* stmp,
+                               unsigned short* stile, unsigned short* qidx, bool keep) {
   const int per_row = R.rw + 1;
   const int64_t ubase = (int64_t)R.unit * g.tpl;
   for (int p = threadIdx.x; p < R.total; p += kWG) {
@@ -763,6 +763,7 @@ __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, co
     for (int q = t0; q < t1; ++q) rk += stmp[q] < hp;
     const int slot = slot_of(L, lo / per_row, p);
     rec[t0 + rk] = make_float4(a.xs[slot], a.ys[slot], a.es[slot], __int_as_float(hp));
+    stile[t0 + rk] = (unsigned short)lo;
   }
   // quads anchored at region tiles [qx0, qx1] x [qy0, qy1]
   const int qx0 = max(R.cx0 - 1, 0), qx1 = min(R.cx0 + R.cw - 1, R.rw - 1);
@@ -794,37 +795,35 @@ __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, co
   }
   __syncthreads();
   if (use_quads && L.qtotal <= 4 * g.lds_cap) {
-    // one lane per quad: 4-way merge of its tiles' index-sorted lists
-    for (int q = threadIdx.x; q < nquad; q += kWG) {
-      const int ax = qx0 + q % qw, ay = qy0 + q / qw;
-      const int bx1 = min(ax + 1, R.rw - 1), by1 = min(ay + 1, R.rh - 1);
-      int cur[4], end[4], hd[4];
+    // place every sorted record into each quad that holds its tile
+    for (int p = threadIdx.x; p < R.total; p += kWG) {
+      const int tl = stile[p];
+      const int tr = tl / per_row, tc = tl - tr * per_row;
+      const int hp = __float_as_int(rec[p].w);
+      const int own = p - L.ts[tl];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int ty = (k & 2) ? by1 : ay, tx = (k & 1) ? bx1 : ax;
-        const bool dup = ((k & 2) && by1 == ay) || ((k & 1) && bx1 == ax);  // clamped at the region edge
-        cur[k] = dup ? 0 : L.ts[ty * per_row + tx];
-        end[k] = dup ? 0 : L.ts[ty * per_row + tx + 1];
-        hd[k] = cur[k] < end[k] ? __float_as_int(rec[cur[k]].w) : INT_MAX;
-      }
-      unsigned short* out = qidx + L.qoff[q];
-      for (;;) {
-        const int m = min(min(hd[0], hd[1]), min(hd[2], hd[3]));
-        if (m == INT_MAX) break;
-        int pos = cur[0];
+      for (int dy = 0; dy < 2; ++dy)
 #pragma unroll
-        for (int k = 1; k < 4; ++k)
-          if (hd[k] == m) pos = cur[k];
-        *out++ = (unsigned short)pos;
-        const int np = pos + 1;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          if (hd[k] == m) {
-            cur[k] = np;
-            hd[k] = np < end[k] ? __float_as_int(rec[np].w) : INT_MAX;
-          }
+        for (int dx = 0; dx < 2; ++dx) {
+          const int ax = tc - dx, ay = tr - dy;
+          if (ax < qx0 || ax > qx1 || ay < qy0 || ay > qy1) continue;
+          int pos = own;
+          const int bx1 = min(ax + 1, R.rw - 1), by1 = min(ay + 1, R.rh - 1);
+          for (int ty = ay; ty <= by1; ++ty)
+            for (int tx = ax; tx <= bx1; ++tx) {
+              if (ty == tr && tx == tc) continue;
+              int lo = L.ts[ty * per_row + tx], hi = L.ts[ty * per_row + tx + 1];
+              while (lo < hi) {  // count of entries with index < hp
+                const int mid = (lo + hi) >> 1;
+                if (__float_as_int(rec[mid].w) < hp)
+                  lo = mid + 1;
+                else
+                  hi = mid;
+              }
+              pos += lo - L.ts[ty * per_row + tx];
+            }
+          qidx[L.qoff[(ay - qy0) * qw + (ax - qx0)] + pos] = (unsigned short)p;
         }
-      }
     }
     __syncthreads();
   } else {
@@ -909,7 +908,8 @@ __global__ __launch_bounds__(kWG) void k_density(DescArg<G> dg, Geom g, Arena a)
   __shared__ int s_item;
   float4* rec = reinterpret_cast<float4*>(smem);
   int* stmp = reinterpret_cast<int*>(rec + g.lds_cap);
-  unsigned short* qidx = reinterpret_cast<unsigned short*>(stmp + g.lds_cap);
+  unsigned short* stile = reinterpret_cast<unsigned short*>(stmp + g.lds_cap);
+  unsigned short* qidx = stile + g.lds_cap;
   const int n_items = d.n_events * g.L * g.bpu;
   const bool keep = g.flags & 2u;
   ItemSched st{0, G ? xcc_id() : 0};
@@ -921,7 +921,7 @@ __global__ __launch_bounds__(kWG) void k_density(DescArg<G> dg, Geom g, Arena a)
     region_setup(g, a, R, L);
     if (L.core_lo[R.ch] == 0) continue;
     if (R.total <= g.lds_cap) {
-      density_staged<MAXL>(g, a, R, L, rec, stmp, qidx, keep);
+      density_staged<MAXL>(g, a, R, L, rec, stmp, stile, qidx, keep);
       continue;
     }
     for (int ty = ty0; ty <= ty1; ++ty)
@@ -930,7 +930,7 @@ __global__ __launch_bounds__(kWG) void k_density(DescArg<G> dg, Geom g, Arena a)
         region_setup(g, a, R, L);
         if (L.core_lo[R.ch] == 0) continue;
         if (R.total <= g.lds_cap)
-          density_staged<MAXL>(g, a, R, L, rec, stmp, qidx, keep);
+          density_staged<MAXL>(g, a, R, L, rec, stmp, stile, qidx, keep);
         else
           density_global_region(g, a, R, L, keep);
       }
@@ -1271,9 +1271,9 @@ __global__ void k_set_desc(RunDesc d, RunDesc* dd) {
 // ---------------------------------------------------------------------------
 // Host launches.
 // ---------------------------------------------------------------------------
-// Dynamic LDS of the density kernel: per staged hit a float4 record and an
-// int, plus four 16-bit quad-list entries.
-int lds_bytes_for(int lds_cap) { return lds_cap * (16 + 4 + 8); }
+// Dynamic LDS of the tile-block kernels: per staged hit a float4 record, an
+// int and a 16-bit tile id, plus four 16-bit quad-list entries.
+int lds_bytes_for(int lds_cap) { return lds_cap * (16 + 4 + 2 + 8); }
 // Nearest-higher: per staged hit a float4 record and one queue int.
 int lds_bytes_nh(int lds_cap) { return lds_cap * (16 + 4); }
 
