@@ -127,6 +127,16 @@ int clue_run_batch(clue_ctx *c, int64_t n, int32_t n_events, const int32_t *even
                    uint8_t *is_seed, void *stream);
 
 /*
+ * As clue_run_batch for a contiguous run of events taken from a larger
+ * device pool: event ids lie in [first_event, first_event + n_events) and are
+ * non-decreasing; results equal clue_run_batch with ids - first_event. Lets
+ * a serving loop cluster consecutive pool events with no copy.
+ */
+int clue_run_batch_range(clue_ctx *c, int64_t n, int32_t first_event, int32_t n_events,
+                         const int32_t *event, const float *x, const float *y, const int32_t *layer,
+                         const float *energy, int32_t *cluster_id, uint8_t *is_seed, void *stream);
+
+/*
  * Copy the last run's per-hit intermediates into caller DEVICE buffers, in the
  * caller's hit order: rho float32[n] (Eq. 3), nh int32[n] (event-local, -1 if
  * none), delta2 float32[n] (squared separation, +inf if none). Any pointer may

@@ -118,6 +118,21 @@ class Context:
         self._last_n = n
         return cluster_id, is_seed
 
+    def run_batch_range(self, first_event, n_events, event, x, y, layer, energy, cluster_id, is_seed,
+                        stream=None):
+        """Batched form over a contiguous run of pool events with ids in
+        [first_event, first_event + n_events); tensors may be views into a pool."""
+        torch = _torch()
+        n = int(x.numel())
+        self._check(self._L.clue_run_batch_range(
+            self._ctx, n, int(first_event), int(n_events), self._dev(event, torch.int32, "event", n),
+            self._dev(x, torch.float32, "x", n), self._dev(y, torch.float32, "y", n),
+            self._dev(layer, torch.int32, "layer", n), self._dev(energy, torch.float32, "energy", n),
+            self._dev(cluster_id, torch.int32, "cluster_id", n), self._dev(is_seed, torch.uint8, "is_seed", n),
+            self._stream(stream)))
+        self._last_n = n
+        return cluster_id, is_seed
+
     def intermediates(self, stream=None):
         """rho, nh (event-local) and delta^2 of the last run (needs KEEP_INTERMEDIATES)."""
         torch = _torch()

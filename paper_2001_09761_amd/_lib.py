@@ -75,6 +75,7 @@ def load(path: str = LIB_PATH):
         "clue_footprint_bytes": ([ctypes.POINTER(ClueParams), i64, i32, ctypes.POINTER(u64)], ctypes.c_int),
         "clue_run": ([P, i64, P, P, P, P, P, P, P], ctypes.c_int),
         "clue_run_batch": ([P, i64, i32, P, P, P, P, P, P, P, P], ctypes.c_int),
+        "clue_run_batch_range": ([P, i64, i32, i32, P, P, P, P, P, P, P, P], ctypes.c_int),
         "clue_get_intermediates": ([P, P, P, P, P], ctypes.c_int),
         "clue_get_followers": ([P, P, P, ctypes.POINTER(i64), P], ctypes.c_int),
         "clue_status": ([P, P], ctypes.c_int),

@@ -425,9 +425,9 @@ static int validate_inputs(clue_ctx* c, const RunDesc& d, hipStream_t s) {
   return CLUE_OK;
 }
 
-static int run_common(clue_ctx* c, int64_t n, int32_t n_events, const int32_t* event, const float* x, const float* y,
-                      const int32_t* layer, const float* energy, int32_t* cid, uint8_t* seed, void* stream,
-                      bool batched) {
+static int run_common(clue_ctx* c, int64_t n, int32_t n_events, int32_t event_base, const int32_t* event,
+                      const float* x, const float* y, const int32_t* layer, const float* energy, int32_t* cid,
+                      uint8_t* seed, void* stream, bool batched) {
   int rc = check_run_args(c, n, n_events, x, y, layer, energy, cid, seed);
   if (rc != CLUE_OK) return rc;
   if (batched && n_events > 1 && n > 0 && !event) return set_err(c, CLUE_ERR_ARG, "null event ids");
@@ -447,6 +447,7 @@ static int run_common(clue_ctx* c, int64_t n, int32_t n_events, const int32_t* e
   d.e = energy;
   d.layer = layer;
   d.event = batched ? event : nullptr;
+  d.event_base = batched ? event_base : 0;
   d.cluster_id = cid;
   d.is_seed = seed;
   if (c->params.flags & CLUE_VALIDATE) {
@@ -478,12 +479,19 @@ static int run_common(clue_ctx* c, int64_t n, int32_t n_events, const int32_t* e
 
 int clue_run(clue_ctx* c, int64_t n, const float* x, const float* y, const int32_t* layer, const float* energy,
              int32_t* cluster_id, uint8_t* is_seed, void* stream) {
-  return run_common(c, n, 1, nullptr, x, y, layer, energy, cluster_id, is_seed, stream, false);
+  return run_common(c, n, 1, 0, nullptr, x, y, layer, energy, cluster_id, is_seed, stream, false);
 }
 
 int clue_run_batch(clue_ctx* c, int64_t n, int32_t n_events, const int32_t* event, const float* x, const float* y,
                    const int32_t* layer, const float* energy, int32_t* cluster_id, uint8_t* is_seed, void* stream) {
-  return run_common(c, n, n_events, event, x, y, layer, energy, cluster_id, is_seed, stream, true);
+  return run_common(c, n, n_events, 0, event, x, y, layer, energy, cluster_id, is_seed, stream, true);
+}
+
+int clue_run_batch_range(clue_ctx* c, int64_t n, int32_t first_event, int32_t n_events, const int32_t* event,
+                         const float* x, const float* y, const int32_t* layer, const float* energy,
+                         int32_t* cluster_id, uint8_t* is_seed, void* stream) {
+  if (first_event < 0) return set_err(c, CLUE_ERR_ARG, "first_event must be >= 0");
+  return run_common(c, n, n_events, first_event, event, x, y, layer, energy, cluster_id, is_seed, stream, true);
 }
 
 int clue_get_intermediates(clue_ctx* c, float* rho, int32_t* nh, float* delta2, void* stream) {

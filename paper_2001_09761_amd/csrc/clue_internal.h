@@ -44,6 +44,7 @@ struct RunDesc {
   const float* e;
   const int32_t* layer;
   const int32_t* event;  // nullptr: single event
+  int32_t event_base;    // event ids are event_base + [0, n_events)
   int32_t* cluster_id;
   uint8_t* is_seed;
 };

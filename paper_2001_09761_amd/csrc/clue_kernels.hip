@@ -143,8 +143,8 @@ __global__ __launch_bounds__(kWG) void k_hist(DescArg<G> dg, Geom g, Arena a) {
     if (valid) {
       int e = 0;
       if (d.event) {
-        e = clampi(d.event[h], 0, d.n_events - 1);
-        const int prev = h == 0 ? -1 : clampi(d.event[h - 1], 0, d.n_events - 1);
+        e = clampi(d.event[h] - d.event_base, 0, d.n_events - 1);
+        const int prev = h == 0 ? -1 : clampi(d.event[h - 1] - d.event_base, 0, d.n_events - 1);
         for (int k = prev + 1; k <= e; ++k) a.ev_start[k] = h;
         if (h == d.n - 1)
           for (int k = e + 1; k <= d.n_events; ++k) a.ev_start[k] = d.n;
@@ -1241,7 +1241,7 @@ __global__ __launch_bounds__(kWG) void k_follow_sort(DescArg<G> dg, Geom g, Aren
       }
       a.flist[j + 1] = v;
     }
-    const int e = d.event ? clampi(d.event[h], 0, d.n_events - 1) : 0;
+    const int e = d.event ? clampi(d.event[h] - d.event_base, 0, d.n_events - 1) : 0;
     const int off = event_first_hit(a, d, e);
     for (int i = b; i < end; ++i) a.flist[i] -= off;
   }
@@ -1257,7 +1257,7 @@ __global__ __launch_bounds__(kWG) void k_validate(RunDesc d, int L, uint32_t* er
     bad |= !isfinite(d.x[h]) || !isfinite(d.y[h]) || !isfinite(d.e[h]);
     bad |= d.layer[h] < 0 || d.layer[h] >= L;
     if (d.event) {
-      bad |= d.event[h] < 0 || d.event[h] >= d.n_events;
+      bad |= d.event[h] < d.event_base || d.event[h] - d.event_base >= d.n_events;
       if (h > 0) bad |= d.event[h] < d.event[h - 1];
     }
   }

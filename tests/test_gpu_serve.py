@@ -1,0 +1,107 @@
+"""GPU: the served form and the autotuner.
+
+Each event's result is the same alone and in the mix (continuous batching
+over two slots on separate streams), bit for bit, and equal to the oracle;
+clue_run_batch_range equals clue_run_batch; the autotuner's candidates all
+reproduce the reference output."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import to_dev
+from paper_2001_09761_amd import gen
+
+pytestmark = pytest.mark.gpu
+NT = min(16, os.cpu_count() or 1)
+
+
+def _params(n_layers):
+    return dict(gen.DEFAULT_PARAMS, extent=200.0, n_layers=n_layers)
+
+
+def _events(n, n_layers=8, seed=11):
+    return [gen.config4_event(e, seed=seed, n_layers=n_layers) for e in range(n)]
+
+
+def test_served_results_equal_alone_and_oracle():
+    import torch
+    import paper_2001_09761_amd as clue
+    from paper_2001_09761_amd.serve import GpuPoolBackend, Scheduler, make_pool
+    dev = torch.device("cuda", 0)
+    evs = _events(40)
+    p = _params(8)
+    pool = make_pool(evs, dev)
+    n_hits = [e["x"].size for e in evs]
+    cap = 12 * max(n_hits)
+    be = GpuPoolBackend(p, pool, slots=2, max_batch_hits=cap, max_batch_events=12)
+    arrivals = gen.poisson_arrivals(20000.0, len(evs))  # fast enough that batches form
+    st = Scheduler(be, hbm_budget_bytes=0, max_batch_hits=cap, max_batch_events=12).run(arrivals, n_hits)
+    torch.cuda.synchronize()
+    summ = st.summary()
+    assert summ["events"] == len(evs) and summ["max_batch_events"] > 1, summ
+    got_cid = pool["cluster_id"].cpu().numpy()
+    got_seed = pool["is_seed"].cpu().numpy()
+    with clue.Context(p["dc"], p["rho_c"], p["delta_c"], p["delta_o"], max_hits=max(n_hits), extent=200.0,
+                      n_layers=8) as ctx:
+        for i, ev in enumerate(evs):
+            a, z = int(pool["offsets"][i]), int(pool["offsets"][i + 1])
+            t = to_dev(ev, dev)
+            cid, seed = ctx.run(t["x"], t["y"], t["layer"], t["energy"])
+            assert np.array_equal(got_cid[a:z], cid.cpu().numpy()), f"event {i} differs in the mix"
+            assert np.array_equal(got_seed[a:z], seed.cpu().numpy()), f"event {i} seeds differ in the mix"
+            if i % 8 == 0:
+                ref = oracle.run_event(ev, p, n_threads=NT, want=())
+                assert np.array_equal(got_cid[a:z], ref["cluster_id"])
+        ctx.status()
+    be.close()
+
+
+def test_run_batch_range_equals_run_batch():
+    import torch
+    import paper_2001_09761_amd as clue
+    dev = torch.device("cuda", 0)
+    evs = _events(6, seed=13)
+    b = gen.concat_events(evs)
+    t = to_dev(b, dev)
+    n = b["x"].size
+    p = _params(8)
+    with clue.Context(p["dc"], p["rho_c"], p["delta_c"], p["delta_o"], max_hits=n, max_events=6, extent=200.0,
+                      n_layers=8) as ctx:
+        cid, seed = ctx.run_batch(t["event"], 6, t["x"], t["y"], t["layer"], t["energy"])
+        cid, seed = cid.clone(), seed.clone()
+        # events 2..4 of a pool whose ids start at 100
+        offs = np.concatenate([[0], np.cumsum([e["x"].size for e in evs])])
+        a, z = int(offs[2]), int(offs[5])
+        ev_ids = (t["event"][a:z] + 98).contiguous()
+        c2 = torch.empty(z - a, dtype=torch.int32, device=dev)
+        s2 = torch.empty(z - a, dtype=torch.uint8, device=dev)
+        ctx.run_batch_range(100, 3, ev_ids, t["x"][a:z], t["y"][a:z], t["layer"][a:z], t["energy"][a:z], c2, s2)
+        torch.cuda.synchronize()
+        ctx.status()
+        assert torch.equal(c2, cid[a:z]) and torch.equal(s2, seed[a:z])
+
+
+def test_autotuner_keeps_outputs_identical(tmp_path):
+    import torch
+    import paper_2001_09761_amd as clue
+    from paper_2001_09761_amd import autotune
+    dev = torch.device("cuda", 0)
+    evs = _events(4, seed=17)
+    b = gen.concat_events(evs)
+    t = to_dev(b, dev)
+    p = _params(8)
+    space = [("density_quads", [1, 2]), ("block", [(8, 8), (4, 4)]), ("tile_size", [5.0]),
+             ("nh_first_radius", [0.0, 1.0]), ("threads_per_query", [1, 4]), ("lds_cap", [256])]
+    with clue.Context(p["dc"], p["rho_c"], p["delta_c"], p["delta_o"], max_hits=b["x"].size, max_events=4,
+                      extent=200.0, n_layers=8) as ctx:
+        best, table = autotune.autotune(ctx, t, 4, p, reps=1, space=space, log=None)
+        assert len(table) >= 8 and best["ms"] > 0
+        cid, _ = ctx.run_batch(t["event"], 4, t["x"], t["y"], t["layer"], t["energy"])
+        ref = oracle.run_event(b, p, n_threads=NT, want=())
+        assert np.array_equal(cid.cpu().numpy(), ref["cluster_id"])
+        # cache round trip
+        key = autotune.cache_key(p, b["x"].size, 4)
+        autotune.store_cached(key, best, str(tmp_path / "t.json"))
+        assert autotune.load_cached(key, str(tmp_path / "t.json"))["tile_size"] == best["tile_size"]

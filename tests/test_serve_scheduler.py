@@ -1,0 +1,131 @@
+"""Serving scheduler on the CPU: oracle-backed fake backend, virtual clock.
+
+Checks admission by HBM budget, continuous batching of consecutive pool
+events, slot concurrency, failure re-queueing, and that every event's result
+equals the result of clustering it alone."""
+import numpy as np
+import pytest
+
+import oracle
+from fake_backend import FakeBackend
+from oracle_cases import adversarial_event
+from paper_2001_09761_amd import gen
+from paper_2001_09761_amd.serve import POOL_BYTES_PER_HIT, Scheduler
+
+P = dict(dc=2.0, rho_c=5.0, delta_c=2.0, delta_o=4.0, bounds=(0, 0, 20, 20), n_layers=3)
+
+
+def _events(n=12):
+    return [adversarial_event(100 + i, n=60 + 13 * i, n_layers=3) for i in range(n)]
+
+
+def _alone(ev):
+    return oracle.run(ev["x"], ev["y"], ev["layer"], ev["energy"], dc=P["dc"], rho_c=P["rho_c"],
+                      delta_c=P["delta_c"], delta_o=P["delta_o"], bounds=P["bounds"], n_layers=3, want=())
+
+
+def _check_results(be, evs):
+    for i, ev in enumerate(evs):
+        a, z = int(be.offsets[i]), int(be.offsets[i + 1])
+        ref = _alone(ev)
+        assert np.array_equal(be.cluster_id[a:z], ref["cluster_id"]), i
+        assert np.array_equal(be.is_seed[a:z], ref["is_seed"]), i
+
+
+def _check_times(stats):
+    for r in stats.records:
+        assert r.t_arrival <= r.t_admit <= r.t_launch <= r.t_done
+
+
+def test_all_events_served_and_equal_alone():
+    evs = _events()
+    be = FakeBackend(evs, P, slots=2)
+    n_hits = [e["x"].size for e in evs]
+    arrivals = gen.poisson_arrivals(2000.0, len(evs))
+    st = Scheduler(be, max_batch_hits=10_000, max_batch_events=64).run(arrivals, n_hits)
+    _check_results(be, evs)
+    _check_times(st)
+    assert sum(b[2] for b in st.batches) == len(evs)
+
+
+def test_continuous_batching_forms_multi_event_batches():
+    evs = _events(20)
+    # slow service, fast arrivals: events queue up behind the busy slot
+    be = FakeBackend(evs, P, slots=1, service_time=lambda h: 5e-3)
+    arrivals = np.linspace(0, 2e-3, len(evs))
+    st = Scheduler(be, max_batch_hits=10_000, max_batch_events=5).run(arrivals, [e["x"].size for e in evs])
+    sizes = [b[2] for b in st.batches]
+    assert sizes[0] == 1 and max(sizes) == 5 and sum(sizes) == 20
+    # each batch is a run of consecutive pool events
+    for slot, first, count, hits, *_ in st.batches:
+        assert hits == sum(evs[i]["x"].size for i in range(first, first + count))
+    _check_results(be, evs)
+
+
+def test_batch_respects_hit_capacity():
+    evs = _events(10)
+    n_hits = [e["x"].size for e in evs]
+    cap = max(n_hits) + 10
+    be = FakeBackend(evs, P, slots=1, service_time=lambda h: 5e-3)
+    st = Scheduler(be, max_batch_hits=cap, max_batch_events=64).run(np.zeros(len(evs)), n_hits)
+    assert all(b[3] <= cap for b in st.batches)
+    _check_results(be, evs)
+
+
+def test_hbm_budget_limits_inflight_events():
+    evs = _events(8)
+    n_hits = [e["x"].size for e in evs]
+    be = FakeBackend(evs, P, slots=3, slot_bytes=1000)
+    budget = 3 * 1000 + max(n_hits) * POOL_BYTES_PER_HIT  # room for one event at a time
+    st = Scheduler(be, hbm_budget_bytes=budget, max_batch_hits=10_000, max_batch_events=64).run(
+        np.zeros(len(evs)), n_hits)
+    assert st.max_inflight_bytes <= budget - 3 * 1000
+    # at every moment the events of overlapping batches fit the budget
+    for b in st.batches:
+        live = [c for c in st.batches if c[4] <= b[4] < c[5]]
+        assert sum(c[3] for c in live) * POOL_BYTES_PER_HIT <= budget - 3 * 1000
+    _check_results(be, evs)
+    # without a budget the same arrivals put more in flight at once
+    be2 = FakeBackend(evs, P, slots=3, slot_bytes=1000)
+    st2 = Scheduler(be2, max_batch_hits=10_000, max_batch_events=64).run(np.zeros(len(evs)), n_hits)
+    assert st2.max_inflight_bytes > budget - 3 * 1000
+
+
+def test_slots_overlap_when_budget_allows():
+    evs = _events(6)
+    be = FakeBackend(evs, P, slots=3, service_time=lambda h: 1e-2)
+    st = Scheduler(be, max_batch_hits=10_000, max_batch_events=1).run(np.zeros(6), [e["x"].size for e in evs])
+    starts = [b[4] for b in st.batches[:3]]
+    assert len(set(b[0] for b in st.batches[:3])) == 3 and max(starts) - min(starts) < 1e-2
+
+
+def test_failed_slot_requeues_and_results_still_equal_alone():
+    evs = _events(10)
+    be = FakeBackend(evs, P, slots=2, fail_once_on_slot=0, service_time=lambda h: 2e-3)
+    st = Scheduler(be, max_batch_hits=10_000, max_batch_events=4).run(np.zeros(len(evs)),
+                                                                         [e["x"].size for e in evs])
+    assert st.failures == 1
+    assert any(r.attempts == 2 for r in st.records)
+    _check_results(be, evs)
+    _check_times(st)
+
+
+def test_event_larger_than_budget_or_slot_is_rejected():
+    evs = _events(3)
+    n_hits = [e["x"].size for e in evs]
+    be = FakeBackend(evs, P, slots=1, slot_bytes=100)
+    with pytest.raises(ValueError):
+        Scheduler(be, hbm_budget_bytes=100 + 10, max_batch_hits=10_000, max_batch_events=8).run(np.zeros(3), n_hits)
+    with pytest.raises(ValueError):
+        Scheduler(be, max_batch_hits=10, max_batch_events=8).run(np.zeros(3), n_hits)
+    with pytest.raises(ValueError):
+        Scheduler(be, hbm_budget_bytes=50, max_batch_hits=10_000, max_batch_events=8)
+
+
+def test_summary_fields():
+    evs = _events(5)
+    be = FakeBackend(evs, P, slots=2)
+    st = Scheduler(be, max_batch_hits=10_000, max_batch_events=8).run(gen.poisson_arrivals(500.0, 5),
+                                                                        [e["x"].size for e in evs])
+    s = st.summary()
+    assert s["events"] == 5 and s["p99_ms"] >= s["p50_ms"] > 0 and s["hits"] == sum(e["x"].size for e in evs)
