@@ -1,12 +1,16 @@
 """CLUE benchmark on one MI355X: hits clustered per second, plain vs batched,
 with per-stage times, the dominant kernel against the HBM roofline, event
-latency percentiles, and the CPU oracle timed on the host cores.
+latency percentiles (single event and served stream), and the CPU oracle
+timed on the host cores.
 
-Workload: the 1M-hit event (100 layers x 10,000 hits, 475 Gaussian clusters
-of 20 hits per layer plus 5 % noise, 200x200 cm, dc=2, rho_c=5, delta_c=2,
-delta_o=4). One step is one batched pass (clue_run_batch) over a batch of
-distinct such events, inputs resident in HBM. The plain form (one
-clue_run per event) is timed on the same events.
+Headline workload: the 1M-hit event (100 layers x 10,000 hits, 475 Gaussian
+clusters of 20 hits per layer plus 5 % noise, 200x200 cm, dc=2, rho_c=5,
+delta_c=2, delta_o=4). One step is one batched pass (clue_run_batch, HIP
+graph of persistent per-stage kernels) over a batch of distinct such events,
+inputs resident in HBM; the plain form (one clue_run per event) is timed on
+the same events. Also reported: the 64-event batch of 100 layers x
+U[1000, 10000] hits (plain vs batched), and a served Poisson stream of such
+events with p50/p99 latency.
 
     python bench.py [--steps K] [--warmup W] [--events B]
 
@@ -31,14 +35,14 @@ HBM_PEAK_GBPS = 8000.0
 # the same accounting: grid 16 + density 20 + nearest-higher 24 +
 # decision/followers 17 + expansion 8 = 85 B per hit.
 ALG_BYTES = {
-    "grid_hist": 16.0,       # x, y, layer (+ per-hit event id 4 B in batches, not counted) -> tile id
+    "grid_hist": 16.0,       # x, y, layer in; tile id out
     "grid_scatter": 16.0,
     "density": 20.0,         # x, y, E, index in; rho out
     "nearest_higher": 24.0,  # x, y, rho, index in; nearest-higher link and separation out
     "labels": 8.0,           # link in, cluster id out
 }
 PIPELINE_ALG_BYTES = 85.0
-PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic_nearest_higher_cfg2x32.json")
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
 
 
 def kernel_source_sha() -> str:
@@ -72,6 +76,20 @@ def cpu_baseline(events, params, budget_s=12.0):
                       f"{threads} threads over (event, layer) units, {dt:.2f} s wall"}
 
 
+def apply_tuning(ctx, batch, n_events, params, log):
+    """Tuning from the package's MI355X cache, else from an autotuner run."""
+    from paper_2001_09761_amd import autotune
+    key = autotune.cache_key(params, int(batch["x"].numel()), n_events)
+    t = autotune.load_cached(key, autotune.SHIPPED_CACHE)
+    if t is not None:
+        t = dict(t)
+        t["block"] = tuple(t["block"])
+        autotune._apply(ctx, t)
+        return t, "shipped cache"
+    t, how = autotune.tuned_context_setup(ctx, batch, n_events, params, log=log)
+    return t, how
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -79,12 +97,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--events", type=int, default=32, help="distinct 1M-hit events per batch")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-extras", action="store_true", help="headline only (no 64-event or served runs)")
+    ap.add_argument("--serve-rate", type=float, default=2000.0, help="offered events/s of the served stream")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the clustering of independent "
-              f"events would shard across GPUs with no exchange, but that path is not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); independent events would shard "
+              f"across GPUs with no exchange, but that path is not built.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -95,6 +115,7 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    log = lambda s: print(s, file=sys.stderr, flush=True)  # noqa: E731
 
     if args.calibrate_copy:
         a = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
@@ -108,10 +129,8 @@ def main():
 
     # ---- inputs: B distinct 1M-hit events, resident in HBM ----------------
     t_gen = time.perf_counter()
-    events = []
-    for e in range(args.events):
-        ev, params = gen.config2(seed=1, event_index=e)
-        events.append(ev)
+    events = [gen.config2(seed=1, event_index=e)[0] for e in range(args.events)]
+    params = dict(gen.DEFAULT_PARAMS, extent=200.0, n_layers=100)
     batch = gen.concat_events(events)
     n = int(batch["x"].size)
     offs = np.concatenate([[0], np.cumsum([ev["x"].size for ev in events])])
@@ -121,6 +140,7 @@ def main():
     seed = torch.empty(n, dtype=torch.uint8, device=dev)
     ctx = clue.Context(params["dc"], params["rho_c"], params["delta_c"], params["delta_o"], max_hits=n,
                        max_events=args.events, extent=params["extent"], n_layers=params["n_layers"])
+    tuning, tuning_src = apply_tuning(ctx, d, args.events, params, log)
     stream = torch.cuda.current_stream()
 
     def step_batched():
@@ -163,7 +183,7 @@ def main():
     # ---- single-event latency (plain form, device time) ------------------
     lat_plain = []
     a, b = int(offs[0]), int(offs[1])
-    for rep in range(40):
+    for _ in range(40):
         s0 = torch.cuda.Event(enable_timing=True)
         s1 = torch.cuda.Event(enable_timing=True)
         s0.record(stream)
@@ -197,6 +217,8 @@ def main():
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
                 "alg_bytes_per_hit": ALG_BYTES[dom], "hits_per_launch": n, "avg_launch_ms": round(dom_ms, 4)}
+    ctx.close()
+    del d, cid, seed
 
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "hits/s", "n_gpus": 1, "steps": args.steps,
@@ -206,7 +228,7 @@ def main():
                                f"noise per layer), {args.events} distinct events per batched step",
                    "hits_per_step": n, "events_per_step": args.events, "dc": params["dc"],
                    "rho_c": params["rho_c"], "delta_c": params["delta_c"], "delta_o": params["delta_o"],
-                   "tuning": ctx.tuning(), "parallelism": "single GPU"},
+                   "tuning": tuning, "tuning_source": tuning_src, "parallelism": "single GPU"},
         "batched_hits_per_s": round(value, 1),
         "plain_hits_per_s": round(plain_value, 1),
         "batched_over_plain": round(value / plain_value, 3),
@@ -219,10 +241,78 @@ def main():
         "roofline": roofline,
         "input_generation_s": round(t_gen, 2),
     }
+
+    if not args.no_extras:
+        out.update(extras(args, params, log))
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(events, params)
-    ctx.close()
     print(json.dumps(out), flush=True)
+
+
+def extras(args, params, log):
+    """64-event batch (plain vs batched) and a served Poisson stream."""
+    import numpy as np
+    import torch
+
+    import paper_2001_09761_amd as clue
+    from paper_2001_09761_amd import gen
+    from paper_2001_09761_amd.serve import GpuPoolBackend, Scheduler, make_pool
+
+    dev = torch.device("cuda", 0)
+    res = {}
+    # 64 events x 100 layers x U[1000, 10000] hits
+    evs = [gen.config4_event(e) for e in range(64)]
+    b = gen.concat_events(evs)
+    n = int(b["x"].size)
+    d = {k: torch.from_numpy(v).to(dev) for k, v in b.items() if isinstance(v, np.ndarray)}
+    offs = np.concatenate([[0], np.cumsum([e["x"].size for e in evs])])
+    with clue.Context(params["dc"], params["rho_c"], params["delta_c"], params["delta_o"], max_hits=n,
+                      max_events=64, extent=200.0, n_layers=100) as ctx:
+        tuning, _ = apply_tuning(ctx, d, 64, params, log)
+        cid = torch.empty(n, dtype=torch.int32, device=dev)
+        seed = torch.empty(n, dtype=torch.uint8, device=dev)
+
+        def batched():
+            ctx.run_batch(d["event"], 64, d["x"], d["y"], d["layer"], d["energy"], cid, seed)
+
+        def plain():
+            for e in range(64):
+                a, z = int(offs[e]), int(offs[e + 1])
+                ctx.run(d["x"][a:z], d["y"][a:z], d["layer"][a:z], d["energy"][a:z], cid[a:z], seed[a:z])
+
+        tb = []
+        for fn in (batched, plain):
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(3):
+                fn()
+            torch.cuda.synchronize()
+            tb.append((time.perf_counter() - t0) / 3)
+        ctx.status()
+    res["batch64"] = {"workload": "64 events x 100 layers x U[1000,10000] hits", "hits": n,
+                      "batched_hits_per_s": round(n / tb[0], 1), "plain_hits_per_s": round(n / tb[1], 1),
+                      "batched_over_plain": round(tb[1] / tb[0], 3), "tuning": tuning}
+    del d
+
+    # served stream: Poisson arrivals of such events, pool of 64 distinct events x4
+    pool_events = evs * 4
+    pool = make_pool(pool_events, dev)
+    n_hits = [e["x"].size for e in pool_events]
+    cap = 8 * max(n_hits)
+    be = GpuPoolBackend(params, pool, slots=2, max_batch_hits=cap, max_batch_events=8,
+                        tuning={k: v for k, v in dict(tuning).items() if k in ("tile_size", "threads_per_query",
+                                                                             "lds_cap", "nh_first_radius",
+                                                                             "density_quads")})
+    arrivals = gen.poisson_arrivals(args.serve_rate, len(pool_events))
+    sch = Scheduler(be, hbm_budget_bytes=64 << 30, max_batch_hits=cap, max_batch_events=8)
+    st = sch.run(arrivals, n_hits)
+    s = st.summary()
+    res["serving"] = {"workload": "Poisson stream of 100-layer x U[1000,10000]-hit events, device-resident pool",
+                      "offered_events_per_s": args.serve_rate, "slots": 2, "hbm_budget_bytes": 64 << 30,
+                      **{k: (round(v, 4) if isinstance(v, float) else v) for k, v in s.items()}}
+    be.close()
+    return res
 
 
 if __name__ == "__main__":

@@ -16,7 +16,11 @@ import math
 import os
 import time
 
+import numpy as np
+
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "clue_mi355x_tuning.json")
+# Tunings measured on MI355X for the benchmark workloads, shipped with the package.
+SHIPPED_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_mi355x.json")
 
 # Axes searched in this order; each axis keeps the best value found so far.
 def default_space(params):
@@ -157,3 +161,41 @@ def tuned_context_setup(ctx, batch, n_events, params, *, cache_path=DEFAULT_CACH
     best["tuned_seconds"] = round(time.time() - t0, 1)
     store_cached(key, best, cache_path)
     return best, "tuned"
+
+
+def _main():
+    """Tunes the batched form on a synthetic workload and stores the result
+    in a JSON cache: ``python -m paper_2001_09761_amd.autotune --events 32``."""
+    import argparse
+    import json as _json
+
+    import torch
+
+    import paper_2001_09761_amd as clue
+    from paper_2001_09761_amd import gen
+
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", choices=["cfg2", "cfg4"], default="cfg2")
+    ap.add_argument("--events", type=int, default=32)
+    ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--out", default=DEFAULT_CACHE)
+    args = ap.parse_args()
+    dev = torch.device("cuda", 0)
+    if args.workload == "cfg2":
+        evs = [gen.config2(seed=1, event_index=e)[0] for e in range(args.events)]
+    else:
+        evs = [gen.config4_event(e) for e in range(args.events)]
+    params = dict(gen.DEFAULT_PARAMS, extent=200.0, n_layers=100)
+    b = gen.concat_events(evs)
+    batch = {k: torch.from_numpy(v).to(dev) for k, v in b.items() if isinstance(v, np.ndarray)}
+    ctx = clue.Context(params["dc"], params["rho_c"], params["delta_c"], params["delta_o"], max_hits=b["x"].size,
+                       max_events=args.events, extent=200.0, n_layers=100)
+    best, table = autotune(ctx, batch, args.events, params, reps=args.reps, log=lambda s: print(s, flush=True))
+    key = cache_key(params, b["x"].size, args.events)
+    store_cached(key, {k: v for k, v in best.items()}, args.out)
+    print(_json.dumps({"key": key, "best": best}), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    _main()
