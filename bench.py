@@ -42,7 +42,7 @@ ALG_BYTES = {
     "labels": 8.0,           # link in, cluster id out
 }
 PIPELINE_ALG_BYTES = 85.0
-PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "density_1M-hit-x32_traffic.json")
 
 
 def kernel_source_sha() -> str:
@@ -101,7 +101,14 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=2000.0, help="offered events/s of the served stream")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB device copy (HBM counter calibration)")
+    ap.add_argument("--traffic-summary", metavar="DIR",
+                    help="reduce rocprofv3 --pmc runs under DIR (fetch/, write/, copy_fetch/, copy_write/) "
+                         "to the per-launch HBM traffic of the dominant kernel and write it to profiles/")
+    ap.add_argument("--stage", default="density", help="stage whose kernel --traffic-summary reduces")
     args = ap.parse_args()
+    if args.traffic_summary:
+        traffic_summary(args.traffic_summary, args.stage, args.events)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); independent events would shard "
               f"across GPUs with no exchange, but that path is not built.", file=sys.stderr)
@@ -118,13 +125,14 @@ def main():
     log = lambda s: print(s, file=sys.stderr, flush=True)  # noqa: E731
 
     if args.calibrate_copy:
+        # one elementwise kernel reading 1 GiB and writing 1 GiB, five times
         a = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
         b = torch.empty_like(a)
         for _ in range(5):
-            b.copy_(a)
+            torch.neg(a, out=b)
         torch.cuda.synchronize()
-        print(json.dumps({"calibration": "copy", "bytes_read": a.numel() * 4, "bytes_written": b.numel() * 4,
-                          "dispatches": 5}))
+        print(json.dumps({"calibration": "copy", "kernel": "neg", "bytes_read": a.numel() * 4,
+                          "bytes_written": b.numel() * 4, "dispatches": 5}))
         return
 
     # ---- inputs: B distinct 1M-hit events, resident in HBM ----------------
@@ -247,6 +255,56 @@ def main():
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(events, params)
     print(json.dumps(out), flush=True)
+
+
+STAGE_KERNEL = {"grid_hist": "k_hist<true", "grid_scatter": "k_scatter<true", "density": "k_density<true",
+                "nearest_higher": "k_nearest_higher<true", "labels": "k_label<true"}
+
+
+def _pmc_rows(d):
+    """(kernel name, counter name, value) of every dispatch in the counter CSVs under d."""
+    import csv
+    import glob
+    rows = []
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                rows.append((r["Kernel_Name"], r["Counter_Name"], float(r["Counter_Value"])))
+    if not rows:
+        raise SystemExit(f"no counter_collection.csv under {d}")
+    return rows
+
+
+def _mean_counter(rows, counter, match, exclude=None):
+    v = [val for name, c, val in rows if c == counter and match in name and not (exclude and exclude in name)]
+    if not v:
+        names = sorted({name for name, *_ in rows})
+        raise SystemExit(f"no {counter} for a kernel matching {match!r}; kernels: {names[:20]}")
+    return sum(v) / len(v), len(v)
+
+
+def traffic_summary(d, stage, n_events):
+    """HBM bytes per launch of one stage's batched kernel: FETCH_SIZE and
+    WRITE_SIZE (KiB per dispatch) averaged over its dispatches, each scaled by
+    the ratio of known bytes to what the same counter reads for the 1 GiB
+    elementwise copy (torch.neg)."""
+    kname = STAGE_KERNEL[stage]
+    f_k, nf = _mean_counter(_pmc_rows(os.path.join(d, "fetch")), "FETCH_SIZE", kname)
+    w_k, nw = _mean_counter(_pmc_rows(os.path.join(d, "write")), "WRITE_SIZE", kname)
+    f_c, _ = _mean_counter(_pmc_rows(os.path.join(d, "copy_fetch")), "FETCH_SIZE", "neg")
+    w_c, _ = _mean_counter(_pmc_rows(os.path.join(d, "copy_write")), "WRITE_SIZE", "neg")
+    gib = float(1 << 30)
+    sf, sw = gib / (f_c * 1024.0), gib / (w_c * 1024.0)
+    hbm = f_k * 1024.0 * sf + w_k * 1024.0 * sw
+    hits = 10000 * 100 * n_events
+    out = {"stage": stage, "kernel_match": kname, "kernel_source_sha": kernel_source_sha(),
+           "hits_per_launch": hits, "fetch_kib_per_dispatch": f_k, "write_kib_per_dispatch": w_k,
+           "dispatches": [nf, nw], "copy_fetch_kib": f_c, "copy_write_kib": w_c,
+           "scale_fetch": sf, "scale_write": sw, "hbm_bytes_per_launch": hbm,
+           "hbm_bytes_per_hit": hbm / hits, "alg_bytes_per_hit": ALG_BYTES[stage]}
+    with open(PROFILE_TRAFFIC, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out))
 
 
 def extras(args, params, log):
