@@ -36,7 +36,8 @@ HBM_PEAK_GBPS = 8000.0
 # decision/followers 17 + expansion 8 = 85 B per hit.
 ALG_BYTES = {
     "grid_hist": 16.0,       # x, y, layer in; tile id out
-    "grid_scatter": 16.0,
+    "grid_scatter": 12.0,    # tile id, arrival rank in; hit id out
+    "grid_place": 36.0,      # hit id, tile, x, y, E in; tile-ordered x, y, E, id out
     "density": 20.0,         # x, y, E, index in; rho out
     "nearest_higher": 24.0,  # x, y, rho, index in; nearest-higher link and separation out
     "labels": 8.0,           # link in, cluster id out

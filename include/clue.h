@@ -165,8 +165,9 @@ typedef struct {
   float tile_size;          /* grid tile side (cm); must exceed ~1.002 dc */
   int32_t threads_per_query; /* lanes per full-window nearest-higher query: 1, 2, 4, 8 */
   int32_t block_x, block_y; /* tiles per work item (1..16 each) */
-  int32_t lds_cap;          /* hits staged in LDS per work item (64..2048); denser
-                               items are split per tile, then use global memory */
+  int32_t lds_cap;          /* hits staged in LDS per work item (64..2048, default
+                               960); denser items are split into quarter blocks,
+                               then single tiles, then use global memory */
   float nh_first_radius;    /* radius (cm) of the first nearest-higher pass; a hit
                                whose nearest-higher lies strictly inside it skips
                                the full d_m search. 0 or >= d_m: single pass */

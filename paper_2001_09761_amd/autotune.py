@@ -30,7 +30,7 @@ def default_space(params):
     return [
         ("density_quads", [1, 2]),
         ("block", [(8, 8), (8, 4), (16, 8), (4, 4), (16, 16)]),
-        ("lds_cap", [1024, 512, 2048]),
+        ("lds_cap", [960, 1024, 768, 2048, 512]),
         ("tile_size", [base_t, base_t * 1.25, base_t * 1.5]),
         ("nh_first_radius", [0.25 * dm, 0.375 * dm, 0.5 * dm, 0.0]),
         ("threads_per_query", [1, 2, 4]),

@@ -160,6 +160,8 @@ static int plan_geom(const clue_params& p, float tile, int tpq, int bx, int by, 
   g.maxl = maxl;
   g.tpq = tpq;
   g.lds_cap = lds_cap;
+  g.ts_ints = rh * (rw + 1) + 1;
+  g.q_ints = (bx + 1) * (by + 1) + 1;
   return CLUE_OK;
 }
 
@@ -254,14 +256,14 @@ static void drop_graph(clue_ctx* c) {
 }
 
 static void compute_cfg(clue_ctx* c) {
-  const int lds = lds_bytes_for(c->g.lds_cap);
+  const int lds = lds_bytes_for(c->g);
   c->cfg.persist_blocks_stream = c->n_cu * std::min(occupancy_blocks_per_cu(0, 0), 8);
   c->cfg.persist_blocks_rho = c->n_cu * occupancy_blocks_per_cu(1, lds);
-  c->cfg.persist_blocks_nh = c->n_cu * occupancy_blocks_per_cu(3, lds_bytes_nh(c->g.lds_cap));
+  c->cfg.persist_blocks_nh = c->n_cu * occupancy_blocks_per_cu(3, lds_bytes_nh(c->g));
   if (std::getenv("CLUE_VERBOSE"))
     std::fprintf(stderr, "clue: persistent grids stream=%d rho=%d nh=%d scan=%d (cu=%d, lds rho=%d nh=%d)\n",
                  c->cfg.persist_blocks_stream, c->cfg.persist_blocks_rho, c->cfg.persist_blocks_nh,
-                 c->cfg.persist_blocks_scan, c->n_cu, lds, lds_bytes_nh(c->g.lds_cap));
+                 c->cfg.persist_blocks_scan, c->n_cu, lds, lds_bytes_nh(c->g));
   c->cfg.persist_blocks_scan = c->n_cu * std::min(occupancy_blocks_per_cu(2, 0), 4);
 }
 

@@ -12,9 +12,13 @@ constexpr int kScanItems = 16;      // elements per thread in the prefix scans
 constexpr int kScanChunk = kWG * kScanItems;
 constexpr int kMaxRegionTiles = 640;   // staged region tiles, rows x (cols + 1), per workgroup
 constexpr int kMaxRegionRows = 64;
-constexpr int kMaxQuads = 289;        // (block + 1)^2 quads for blocks up to 16x16 tiles
-constexpr int kDefaultLdsCap = 1024;   // staged hits per workgroup (fast path)
+constexpr int kDefaultLdsCap = 960;    // staged hits per workgroup (fast path)
 constexpr int kMaxLdsCap = 2048;
+// Bytes of the density kernel's per-hit LDS arrays (float4 record, 16-bit
+// tile id, four 16-bit quad entries), rounded up to 16.
+__host__ __device__ constexpr int lds_records_density(int lds_cap) { return (lds_cap * (16 + 2 + 8) + 15) & ~15; }
+constexpr int kStagePer = 4;       // staged hits per lane per round (loads in flight)
+constexpr int kPlaceU = 4;         // hits per lane per step of the label kernels
 
 // Counters in device memory, cleared at the start of every run. Each sits on
 // its own 256-byte line so that atomics on different counters do not
@@ -63,6 +67,8 @@ struct Geom {
   int32_t maxl;     // density window tiles per dimension (2 or 3)
   int32_t tpq;      // lanes per nearest-higher query
   int32_t lds_cap;  // staged hits per workgroup
+  int32_t ts_ints;  // LDS ints for a region's tile offsets: rows * (cols + 1) + 1
+  int32_t q_ints;   // LDS ints for the quad-list offsets: (bx + 1) * (by + 1) + 1
   float dc2;        // fl(dc*dc)
   float dm2;        // fl(dm*dm), dm = max(delta_o, delta_c)
   float dcs2;       // fl(delta_c*delta_c)
@@ -81,8 +87,11 @@ struct Geom {
 struct Arena {
   int32_t* key;          // [N]   caller order: global tile id of each hit
   int32_t* rank;         // [N]   caller order: arrival rank within its tile
+                         //       (the grid build keeps arrival-order hit ids and tiles
+                         //       in the rho and parent buffers until each tile is
+                         //       ordered by hit index)
   int32_t* tile_start;   // [TT+1] tile counts, scanned in place into CSR offsets
-  float* xs;             // [N]   slot order (tile CSR)
+  float* xs;             // [N]   slot order (tile CSR; hit index ascending within a tile)
   float* ys;
   float* es;
   int32_t* hs;           // [N]   slot -> caller (batch-global) hit index
@@ -110,7 +119,7 @@ struct Arena {
 enum HitFlags : uint8_t { F_SEED = 1, F_OUTLIER = 2, F_FOLLOWER = 4 };
 
 enum Stage {
-  S_CLEAR = 0, S_HIST, S_SCAN_TILES, S_SCATTER, S_RHO, S_NH, S_SCAN_SEEDS, S_LABEL, S_FOLLOW,
+  S_CLEAR = 0, S_HIST, S_SCAN_TILES, S_SCATTER, S_PLACE, S_RHO, S_NH, S_SCAN_SEEDS, S_LABEL, S_FOLLOW,
   S_COUNT
 };
 extern const char* const kStageNames[S_COUNT];
@@ -131,7 +140,7 @@ hipError_t launch_pipeline(const Geom& g, const Arena& a, const RunDesc& d, cons
 hipError_t launch_set_desc(const RunDesc& d, RunDesc* dd, hipStream_t s);
 hipError_t launch_validate(const Geom& g, const Arena& a, const RunDesc& d, hipStream_t s);
 int occupancy_blocks_per_cu(int which, int lds_bytes);
-int lds_bytes_for(int lds_cap);
-int lds_bytes_nh(int lds_cap);
+int lds_bytes_for(const Geom& g);
+int lds_bytes_nh(const Geom& g);
 
 }  // namespace clue

@@ -4,10 +4,11 @@
 //   k_clear            clears counters, tile counts and scan status
 //   k_hist             fixed grid, part 1: atomic per-tile histogram (Sec. 2.1)
 //   k_scan<TILES>      exclusive prefix scan of the tile counts (decoupled look-back)
-//   k_scatter          fixed grid, part 2: scatter hits into the tile CSR
+//   k_scatter          fixed grid, part 2: hit ids into the tile CSR (arrival order)
+//   k_place            fixed grid, part 3: each tile's records in ascending hit index
 //   k_density          rho (Eq. 3, Algorithm 1) over LDS-staged tile windows,
-//                      summed in ascending hit index by a k-way merge of the
-//                      index-sorted tile lists
+//                      summed in ascending hit index along merged 2x2-tile
+//                      lists of the index-ordered tiles
 //   k_nearest_higher   nh / delta (Eq. 4, Algorithm 2) fused with the seed /
 //                      outlier / follower decision (Sec. 2.2, Algorithm 3)
 //   k_scan<SEEDS>      seed numbering by prefix scan (and follower list offsets)
@@ -26,9 +27,10 @@
 
 namespace clue {
 
-const char* const kStageNames[S_COUNT] = {"clear",   "grid_hist",      "grid_scan",
-                                          "grid_scatter", "density", "nearest_higher",
-                                          "seed_scan", "labels", "follower_lists"};
+const char* const kStageNames[S_COUNT] = {"clear",        "grid_hist",  "grid_scan",
+                                          "grid_scatter", "grid_place", "density",
+                                          "nearest_higher", "seed_scan", "labels",
+                                          "follower_lists"};
 
 // ---------------------------------------------------------------------------
 // Run descriptor: by value (plain launches) or from device memory (graph).
@@ -85,22 +87,6 @@ __device__ __forceinline__ void st_relaxed(int32_t* p, int v) {
 // unvalidated event ids).
 __device__ __forceinline__ int event_first_hit(const Arena& a, const RunDesc& d, int e) {
   return clampi(a.ev_start[e], 0, d.n);
-}
-
-// Event that owns slot s: units are laid out event-major in the tile CSR, so
-// event e owns slots [tile_start[e*L*tpl], tile_start[(e+1)*L*tpl]).
-__device__ __forceinline__ int event_of_slot(const Geom& g, const Arena& a, const RunDesc& d, int s) {
-  if (d.n_events <= 1) return 0;
-  int lo = 0, hi = d.n_events - 1;  // largest e with start(e) <= s
-  const int64_t stride = (int64_t)g.L * g.tpl;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (a.tile_start[(int64_t)mid * stride] <= s)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  return lo;
 }
 
 // ---------------------------------------------------------------------------
@@ -181,19 +167,46 @@ __global__ __launch_bounds__(kWG) void k_hist(DescArg<G> dg, Geom g, Arena a) {
 }
 
 // ---------------------------------------------------------------------------
-// k_scatter: hit h goes to slot tile_start[tile] + rank (arrival order within
-// a tile; the density stage sorts each staged tile by hit index).
+// k_scatter: hit h's id and tile go to slot tile_start[tile] + rank (arrival
+// order within a tile), kept in the rho and parent buffers, which are free
+// until the density stage.
+// k_place: slot by slot, each hit counts the ids of its tile that are smaller
+// than its own and writes its record at that position, so every tile of the
+// CSR lists its hits in ascending hit index. Neighbouring slots share their
+// tile, so the counting loads are broadcasts from lines just read.
 // ---------------------------------------------------------------------------
 template <bool G>
 __global__ __launch_bounds__(kWG) void k_scatter(DescArg<G> dg, Geom g, Arena a) {
   const RunDesc d = dg.get();
+  int* ids = reinterpret_cast<int*>(a.rho);
   const int stride = gridDim.x * kWG;
   for (int h = blockIdx.x * kWG + threadIdx.x; h < d.n; h += stride) {
-    const int s = a.tile_start[a.key[h]] + a.rank[h];
-    a.xs[s] = d.x[h];
-    a.ys[s] = d.y[h];
-    a.es[s] = d.e[h];
-    a.hs[s] = h;
+    const int t = a.key[h];
+    const int s = a.tile_start[t] + a.rank[h];
+    ids[s] = h;
+    a.parent[s] = t;
+  }
+}
+
+template <bool G>
+__global__ __launch_bounds__(kWG) void k_place(DescArg<G> dg, Geom g, Arena a) {
+  const RunDesc d = dg.get();
+  const int* ids = reinterpret_cast<const int*>(a.rho);
+  const int stride = gridDim.x * kWG;
+  for (int s = blockIdx.x * kWG + threadIdx.x; s < d.n; s += stride) {
+    const int h = ids[s];
+    const int t = a.parent[s];
+    const float x = d.x[h], y = d.y[h], e = d.e[h];
+    const int s0 = a.tile_start[t], s1 = a.tile_start[t + 1];
+    int rk = 0;
+    int c = s0;
+    for (; c + 3 < s1; c += 4) rk += (ids[c] < h) + (ids[c + 1] < h) + (ids[c + 2] < h) + (ids[c + 3] < h);
+    for (; c < s1; ++c) rk += ids[c] < h;
+    const int slot = s0 + rk;
+    a.xs[slot] = x;
+    a.ys[slot] = y;
+    a.es[slot] = e;
+    a.hs[slot] = h;
   }
 }
 
@@ -389,8 +402,9 @@ __global__ __launch_bounds__(kWG) void k_scan(DescArg<G> dg, Geom g, Arena a) {
 // Tile-block work items. An item is one (event, layer) unit and a block of
 // bx*by tiles (the core); its staged region adds `halo` tiles around the core
 // (clamped to the grid). Dense blocks whose region does not fit in LDS are
-// processed one core tile at a time, and a tile whose own region still does
-// not fit falls back to global memory.
+// processed as four quarter blocks, a quarter that still does not fit one
+// core tile at a time, and a tile whose own region does not fit falls back
+// to global memory.
 // ---------------------------------------------------------------------------
 struct Region {
   int unit;       // event * L + layer
@@ -402,19 +416,33 @@ struct Region {
   int total;      // hits in the region
 };
 
-// Region metadata in LDS:
+// Region metadata in LDS (pointers into the workgroup's shared memory; ts and
+// qoff live in the dynamic part, sized for the configured block and halo):
 //   ts[r*(rw+1) + c]  LDS offset of region tile (r, c); c = rw is the row end
 //   row_gs[r]         global slot of the first hit of region row r
 //   row_lo[r]         LDS offset of region row r (row_lo[rh] = total)
 //   core_lo[r]        prefix of core-hit counts over core rows
+//   qoff[q]           density: offsets of the merged 2x2-tile lists
 struct RegionLds {
-  int ts[kMaxRegionTiles + 1];
-  int row_gs[kMaxRegionRows];
-  int row_lo[kMaxRegionRows + 1];
-  int core_lo[kMaxRegionRows + 1];
-  int qoff[kMaxQuads + 1];  // density: offsets of the merged 2x2-tile lists
-  int qtotal;
+  int* ts;
+  int* row_gs;
+  int* row_lo;
+  int* core_lo;
+  int* qoff;
+  int* qtotal;
 };
+constexpr int kRowMetaInts = kMaxRegionRows + 2 * (kMaxRegionRows + 1) + 1;
+
+__device__ __forceinline__ RegionLds region_lds(int* row_meta, int* ts, int* qoff) {
+  RegionLds L;
+  L.ts = ts;
+  L.row_gs = row_meta;
+  L.row_lo = row_meta + kMaxRegionRows;
+  L.core_lo = row_meta + 2 * kMaxRegionRows + 1;
+  L.qtotal = row_meta + 3 * kMaxRegionRows + 2;
+  L.qoff = qoff;
+  return L;
+}
 
 __device__ __forceinline__ void item_block(const Geom& g, int item, int& unit, int& tx0, int& ty0, int& tx1,
                                            int& ty1) {
@@ -563,7 +591,7 @@ __device__ __forceinline__ Window query_window(const Geom& g, float w, float xi,
 
 // ---------------------------------------------------------------------------
 // Density (Eq. 3): rho_i = sum of E_j over same-layer j with d2 < dc2, added
-// in ascending j. Staged tiles are index-sorted in LDS; a query first marks
+// in ascending j. Tiles list their hits in ascending index; a query first marks
 // the passing hits of each window tile in a 64-bit mask, then merges only the
 // passing hits of the (at most MAXL x MAXL) sorted tile lists.
 // Records: (x, y, E, hit index as bits).
@@ -701,7 +729,7 @@ __device__ __forceinline__ float density_two_pass(const float4* __restrict__ rec
   return acc;
 }
 
-// Global-memory density: tile lists in arrival order; the neighbours are
+// Global-memory density (tiles too dense to stage): the neighbours are
 // visited in ascending index by repeatedly taking the smallest index above
 // the previous one.
 __device__ __forceinline__ float density_global(const Geom& g, const Arena& a, int64_t ubase, float xi, float yi) {
@@ -729,48 +757,74 @@ __device__ __forceinline__ float density_global(const Geom& g, const Arena& a, i
   return acc;
 }
 
-// Density over a staged region. Tiles are sorted by hit index in LDS
-// (records x, y, E, index). With MAXL == 2 every query window lies inside the
+// Records of the index-sorted list rec[lo, hi) whose hit index is below `k`:
+// a predicated linear count for short lists (independent loads), a binary
+// search otherwise.
+__device__ __forceinline__ int rec_key(const float4* rec, int j) { return __float_as_int(rec[j].w); }
+__device__ __forceinline__ int count_below(const float4* rec, int lo, int hi, int k) {
+  if (hi - lo <= 8) {
+    int c = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (lo + j < hi) c += rec_key(rec, lo + j) < k;
+    return c;
+  }
+  const int base = lo;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (rec_key(rec, mid) < k)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo - base;
+}
+
+// Density over a staged region (records x, y, E, index; each tile in
+// ascending hit index). With MAXL == 2 every query window lies inside the
 // 2x2 tile quad anchored at its lower-left window tile; the quads a core
 // query can use are merged once per region into index-ordered lists (LDS
-// indices into the sorted records), so each query is one linear scan in
-// ascending hit index. Otherwise (or if the quads do not fit) a query merges
-// its window's tile lists itself.
+// indices into the records), so each query is one linear scan in ascending
+// hit index. Otherwise (or if the quads do not fit) a query merges its
+// window's tile lists itself.
 template <int MAXL>
-__device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, const Region& R, RegionLds& L, float4* rec, int* stmp,
-                               unsigned short* stile, unsigned short* qidx, bool keep) {
+__device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, const Region& R, RegionLds& L, float4* rec,
+                                               unsigned short* stile, unsigned short* qidx, bool keep) {
   const int per_row = R.rw + 1;
   const int64_t ubase = (int64_t)R.unit * g.tpl;
-  for (int p = threadIdx.x; p < R.total; p += kWG) {
-    const int r = region_row_of(L, R.rh, p);
-    stmp[p] = a.hs[slot_of(L, r, p)];
+  const int ntl = R.rh * per_row;
+  // region tile of every staged position, two lanes per tile
+  for (int k = threadIdx.x; k < 2 * ntl; k += kWG) {
+    const int tl = k >> 1;
+    if (tl % per_row == R.rw) continue;  // row-end entry
+    const int end = L.ts[tl + 1];
+    for (int p = L.ts[tl] + (k & 1); p < end; p += 2) stile[p] = (unsigned short)tl;
   }
   __syncthreads();
-  // sort each tile by hit index: rank among tile-mates, then place
-  const int last_tile = R.rh * per_row - 1;
-  for (int p = threadIdx.x; p < R.total; p += kWG) {
-    int lo = 0, hi = last_tile;  // last tile entry with ts <= p
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (L.ts[mid] <= p)
-        lo = mid;
-      else
-        hi = mid - 1;
+  // copy the records (tiles are already in ascending hit index); every
+  // global load of a lane is issued before its first LDS store
+  for (int base = 0; base < R.total; base += kStagePer * kWG) {
+    float4 v[kStagePer];
+#pragma unroll
+    for (int k = 0; k < kStagePer; ++k) {
+      const int p = base + (int)threadIdx.x + k * kWG;
+      if (p < R.total) {
+        const int sl = slot_of(L, stile[p] / per_row, p);
+        v[k] = make_float4(a.xs[sl], a.ys[sl], a.es[sl], __int_as_float(a.hs[sl]));
+      }
     }
-    const int t0 = L.ts[lo], t1 = L.ts[lo + 1];
-    const int hp = stmp[p];
-    int rk = 0;
-    for (int q = t0; q < t1; ++q) rk += stmp[q] < hp;
-    const int slot = slot_of(L, lo / per_row, p);
-    rec[t0 + rk] = make_float4(a.xs[slot], a.ys[slot], a.es[slot], __int_as_float(hp));
-    stile[t0 + rk] = (unsigned short)lo;
+#pragma unroll
+    for (int k = 0; k < kStagePer; ++k) {
+      const int p = base + (int)threadIdx.x + k * kWG;
+      if (p < R.total) rec[p] = v[k];
+    }
   }
   // quads anchored at region tiles [qx0, qx1] x [qy0, qy1]
   const int qx0 = max(R.cx0 - 1, 0), qx1 = min(R.cx0 + R.cw - 1, R.rw - 1);
   const int qy0 = max(R.cy0 - 1, 0), qy1 = min(R.cy0 + R.ch - 1, R.rh - 1);
   const int qw = qx1 - qx0 + 1;
   const int nquad = qw * (qy1 - qy0 + 1);
-  bool use_quads = MAXL == 2 && g.density_quads && nquad <= kMaxQuads;
+  bool use_quads = MAXL == 2 && g.density_quads && nquad < g.q_ints;
   if (use_quads) {
     if (threadIdx.x < 64) {
       // quad sizes -> offsets, 64 quads per wave step
@@ -789,40 +843,61 @@ __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, co
       }
       if (threadIdx.x == 0) {
         L.qoff[nquad] = run;
-        L.qtotal = run;
+        *L.qtotal = run;
       }
     }
   }
   __syncthreads();
-  if (use_quads && L.qtotal <= 4 * g.lds_cap) {
-    // place every sorted record into each quad that holds its tile
+  if (use_quads && *L.qtotal <= 4 * g.lds_cap) {
+    // place every sorted record into each quad that holds its tile: its
+    // position there is its rank in its own tile plus, for each other tile
+    // of the quad, the entries with a smaller hit index (each of the up to
+    // eight neighbour tiles is counted once and shared by the quads)
     for (int p = threadIdx.x; p < R.total; p += kWG) {
       const int tl = stile[p];
       const int tr = tl / per_row, tc = tl - tr * per_row;
-      const int hp = __float_as_int(rec[p].w);
+      const int hp = rec_key(rec, p);
       const int own = p - L.ts[tl];
+      bool qv[2][2];
 #pragma unroll
       for (int dy = 0; dy < 2; ++dy)
 #pragma unroll
         for (int dx = 0; dx < 2; ++dx) {
           const int ax = tc - dx, ay = tr - dy;
-          if (ax < qx0 || ax > qx1 || ay < qy0 || ay > qy1) continue;
+          qv[dy][dx] = ax >= qx0 && ax <= qx1 && ay >= qy0 && ay <= qy1;
+        }
+      int below[3][3];
+#pragma unroll
+      for (int oy = -1; oy <= 1; ++oy)
+#pragma unroll
+        for (int ox = -1; ox <= 1; ++ox) {
+          bool need = false;
+#pragma unroll
+          for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 2; ++dx)
+              need |= qv[dy][dx] && (ox == -dx || ox == 1 - dx) && (oy == -dy || oy == 1 - dy);
+          const int nx = tc + ox, ny = tr + oy;
+          need &= (ox != 0 || oy != 0) && nx >= 0 && nx < R.rw && ny >= 0 && ny < R.rh;
+          int c = 0;
+          if (need) {
+            const int nt = ny * per_row + nx;
+            c = count_below(rec, L.ts[nt], L.ts[nt + 1], hp);
+          }
+          below[oy + 1][ox + 1] = c;
+        }
+#pragma unroll
+      for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 2; ++dx) {
+          if (!qv[dy][dx]) continue;
           int pos = own;
-          const int bx1 = min(ax + 1, R.rw - 1), by1 = min(ay + 1, R.rh - 1);
-          for (int ty = ay; ty <= by1; ++ty)
-            for (int tx = ax; tx <= bx1; ++tx) {
-              if (ty == tr && tx == tc) continue;
-              int lo = L.ts[ty * per_row + tx], hi = L.ts[ty * per_row + tx + 1];
-              while (lo < hi) {  // count of entries with index < hp
-                const int mid = (lo + hi) >> 1;
-                if (__float_as_int(rec[mid].w) < hp)
-                  lo = mid + 1;
-                else
-                  hi = mid;
-              }
-              pos += lo - L.ts[ty * per_row + tx];
-            }
-          qidx[L.qoff[(ay - qy0) * qw + (ax - qx0)] + pos] = (unsigned short)p;
+#pragma unroll
+          for (int oy = -dy; oy <= 1 - dy; ++oy)
+#pragma unroll
+            for (int ox = -dx; ox <= 1 - dx; ++ox)
+              if (ox != 0 || oy != 0) pos += below[oy + 1][ox + 1];
+          qidx[L.qoff[(tr - dy - qy0) * qw + (tc - dx - qx0)] + pos] = (unsigned short)p;
         }
     }
     __syncthreads();
@@ -834,7 +909,8 @@ __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, co
     int row, p;
     core_query(L, R, q, row, p);
     const int slot = slot_of(L, row, p);
-    const float xi = a.xs[slot], yi = a.ys[slot];
+    const float4 me = rec[p];
+    const float xi = me.x, yi = me.y;
     const Window W = query_window(g, g.win_dc, xi, yi);
     const int tx0 = W.x0 - R.rx0, tx1 = W.x1 - R.rx0, ty0 = W.y0 - R.ry0, ty1 = W.y1 - R.ry0;
     const bool ok = tx0 >= 0 && ty0 >= 0 && tx1 < R.rw && ty1 < R.rh && tx1 - tx0 < MAXL && ty1 - ty0 < MAXL;
@@ -883,7 +959,7 @@ __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, co
       rho = density_global(g, a, ubase, xi, yi);
     }
     a.rho[slot] = rho;
-    if (keep) a.rho_out[stmp[p]] = rho;
+    if (keep) a.rho_out[__float_as_int(me.w)] = rho;
   }
 }
 
@@ -904,12 +980,13 @@ template <bool G, int MAXL>
 __global__ __launch_bounds__(kWG) void k_density(DescArg<G> dg, Geom g, Arena a) {
   const RunDesc d = dg.get();
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ RegionLds L;
+  __shared__ int s_rows[kRowMetaInts];
   __shared__ int s_item;
   float4* rec = reinterpret_cast<float4*>(smem);
-  int* stmp = reinterpret_cast<int*>(rec + g.lds_cap);
-  unsigned short* stile = reinterpret_cast<unsigned short*>(stmp + g.lds_cap);
+  unsigned short* stile = reinterpret_cast<unsigned short*>(rec + g.lds_cap);
   unsigned short* qidx = stile + g.lds_cap;
+  int* meta = reinterpret_cast<int*>(smem + lds_records_density(g.lds_cap));
+  RegionLds L = region_lds(s_rows, meta, meta + g.ts_ints);
   const int n_items = d.n_events * g.L * g.bpu;
   const bool keep = g.flags & 2u;
   ItemSched st{0, G ? xcc_id() : 0};
@@ -921,18 +998,31 @@ __global__ __launch_bounds__(kWG) void k_density(DescArg<G> dg, Geom g, Arena a)
     region_setup(g, a, R, L);
     if (L.core_lo[R.ch] == 0) continue;
     if (R.total <= g.lds_cap) {
-      density_staged<MAXL>(g, a, R, L, rec, stmp, stile, qidx, keep);
+      density_staged<MAXL>(g, a, R, L, rec, stile, qidx, keep);
       continue;
     }
-    for (int ty = ty0; ty <= ty1; ++ty)
-      for (int tx = tx0; tx <= tx1; ++tx) {
-        make_region(g, unit, tx, ty, tx, ty, R);
+    // too dense: the four quarter blocks, then single tiles
+    const int hx = (tx1 - tx0 + 2) >> 1, hy = (ty1 - ty0 + 2) >> 1;
+    for (int sy = ty0; sy <= ty1; sy += hy)
+      for (int sx = tx0; sx <= tx1; sx += hx) {
+        const int ex = min(sx + hx - 1, tx1), ey = min(sy + hy - 1, ty1);
+        make_region(g, unit, sx, sy, ex, ey, R);
         region_setup(g, a, R, L);
         if (L.core_lo[R.ch] == 0) continue;
-        if (R.total <= g.lds_cap)
-          density_staged<MAXL>(g, a, R, L, rec, stmp, stile, qidx, keep);
-        else
-          density_global_region(g, a, R, L, keep);
+        if (R.total <= g.lds_cap) {
+          density_staged<MAXL>(g, a, R, L, rec, stile, qidx, keep);
+          continue;
+        }
+        for (int ty = sy; ty <= ey; ++ty)
+          for (int tx = sx; tx <= ex; ++tx) {
+            make_region(g, unit, tx, ty, tx, ty, R);
+            region_setup(g, a, R, L);
+            if (L.core_lo[R.ch] == 0) continue;
+            if (R.total <= g.lds_cap)
+              density_staged<MAXL>(g, a, R, L, rec, stile, qidx, keep);
+            else
+              density_global_region(g, a, R, L, keep);
+          }
       }
   }
 }
@@ -950,6 +1040,10 @@ __global__ __launch_bounds__(kWG) void k_density(DescArg<G> dg, Geom g, Arena a)
 __device__ __forceinline__ unsigned ord_f32(float v) {
   const unsigned u = __float_as_uint(__fadd_rn(v, 0.0f));
   return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+// Inverse of ord_f32 (gives +0 for a folded -0, which compares the same).
+__device__ __forceinline__ float ord_inv(unsigned o) {
+  return __uint_as_float((o & 0x80000000u) ? (o & 0x7fffffffu) : ~o);
 }
 __device__ __forceinline__ unsigned long long key64(unsigned hi, unsigned lo) {
   return ((unsigned long long)hi << 32) | lo;
@@ -1051,9 +1145,22 @@ __device__ __forceinline__ void nh_staged(const Geom& g, const Arena& a, const R
                           float4* rec, int* queue, int* s_qn, int ev_first) {
   const int per_row = R.rw + 1;
   const int64_t ubase = (int64_t)R.unit * g.tpl;
-  for (int p = threadIdx.x; p < R.total; p += kWG) {
-    const int s = slot_of(L, region_row_of(L, R.rh, p), p);
-    rec[p] = make_float4(a.xs[s], a.ys[s], __uint_as_float(ord_f32(a.rho[s])), __int_as_float(a.hs[s]));
+  // every global load of a lane is issued before its first LDS store
+  for (int base = 0; base < R.total; base += kStagePer * kWG) {
+    float4 v[kStagePer];
+#pragma unroll
+    for (int k = 0; k < kStagePer; ++k) {
+      const int p = base + (int)threadIdx.x + k * kWG;
+      if (p < R.total) {
+        const int s = slot_of(L, region_row_of(L, R.rh, p), p);
+        v[k] = make_float4(a.xs[s], a.ys[s], a.rho[s], __int_as_float(a.hs[s]));
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kStagePer; ++k) {
+      const int p = base + (int)threadIdx.x + k * kWG;
+      if (p < R.total) rec[p] = make_float4(v[k].x, v[k].y, __uint_as_float(ord_f32(v[k].z)), v[k].w);
+    }
   }
   if (threadIdx.x == 0) *s_qn = 0;
   __syncthreads();
@@ -1073,7 +1180,7 @@ __device__ __forceinline__ void nh_staged(const Geom& g, const Arena& a, const R
         nh_scan_staged<STRICT>(rec, L, per_row, tx0, tx1, ty0, ty1, 0, 1, me.x, me.y, ordi, hi, g.r1sq, b);
         if (b.p >= 0) {
           b.p = slot_of(L, region_row_of(L, R.rh, b.p), b.p);
-          decide_and_store(g, a, d, slot_of(L, row, p), (int)hi, a.rho[slot_of(L, row, p)], b, ev_first);
+          decide_and_store(g, a, d, slot_of(L, row, p), (int)hi, ord_inv(ordi), b, ev_first);
           done = true;
         }
       }
@@ -1091,13 +1198,13 @@ __device__ __forceinline__ void nh_staged(const Geom& g, const Arena& a, const R
     const bool active = qi < nu;
     NhBest b{~0ull, -1};
     int slot = 0;
-    unsigned hi = 0;
+    unsigned hi = 0, ordi = 0;
     if (active) {
       int row, p;
       core_query(L, R, queue[qi], row, p);
       slot = slot_of(L, row, p);
       const float4 me = rec[p];
-      const unsigned ordi = __float_as_uint(me.z);
+      ordi = __float_as_uint(me.z);
       hi = __float_as_uint(me.w);
       const Window W = query_window(g, g.win_dm, me.x, me.y);
       const int tx0 = W.x0 - R.rx0, tx1 = W.x1 - R.rx0, ty0 = W.y0 - R.ry0, ty1 = W.y1 - R.ry0;
@@ -1114,7 +1221,7 @@ __device__ __forceinline__ void nh_staged(const Geom& g, const Arena& a, const R
         b.p = slot_of(L, region_row_of(L, R.rh, b.p), b.p);
       else if (b.p <= -2)
         b.p = -2 - b.p;
-      decide_and_store(g, a, d, slot, (int)hi, a.rho[slot], b, ev_first);
+      decide_and_store(g, a, d, slot, (int)hi, ord_inv(ordi), b, ev_first);
     }
   }
 }
@@ -1164,15 +1271,28 @@ __device__ __forceinline__ void nh_item(const Geom& g, const Arena& a, const Run
     nh_staged<STRICT>(g, a, d, R, L, rec, queue, s_qn, ev_first);
     return;
   }
-  for (int ty = ty0; ty <= ty1; ++ty)
-    for (int tx = tx0; tx <= tx1; ++tx) {
-      make_region(g, unit, tx, ty, tx, ty, R);
+  // too dense: the four quarter blocks, then single tiles
+  const int hx = (tx1 - tx0 + 2) >> 1, hy = (ty1 - ty0 + 2) >> 1;
+  for (int sy = ty0; sy <= ty1; sy += hy)
+    for (int sx = tx0; sx <= tx1; sx += hx) {
+      const int ex = min(sx + hx - 1, tx1), ey = min(sy + hy - 1, ty1);
+      make_region(g, unit, sx, sy, ex, ey, R);
       region_setup(g, a, R, L);
       if (L.core_lo[R.ch] == 0) continue;
-      if (R.total <= g.lds_cap)
+      if (R.total <= g.lds_cap) {
         nh_staged<STRICT>(g, a, d, R, L, rec, queue, s_qn, ev_first);
-      else
-        nh_global_region<STRICT>(g, a, d, R, L, ev_first);
+        continue;
+      }
+      for (int ty = sy; ty <= ey; ++ty)
+        for (int tx = sx; tx <= ex; ++tx) {
+          make_region(g, unit, tx, ty, tx, ty, R);
+          region_setup(g, a, R, L);
+          if (L.core_lo[R.ch] == 0) continue;
+          if (R.total <= g.lds_cap)
+            nh_staged<STRICT>(g, a, d, R, L, rec, queue, s_qn, ev_first);
+          else
+            nh_global_region<STRICT>(g, a, d, R, L, ev_first);
+        }
     }
 }
 
@@ -1180,11 +1300,12 @@ template <bool G, bool STRICT>
 __global__ __launch_bounds__(kWG) void k_nearest_higher(DescArg<G> dg, Geom g, Arena a) {
   const RunDesc d = dg.get();
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ RegionLds L;
+  __shared__ int s_rows[kRowMetaInts];
   __shared__ int s_qn;
   __shared__ int s_item;
   float4* rec = reinterpret_cast<float4*>(smem);
   int* queue = reinterpret_cast<int*>(rec + g.lds_cap);
+  RegionLds L = region_lds(s_rows, queue + g.lds_cap, nullptr);
   const int n_items = d.n_events * g.L * g.bpu;
   ItemSched st{0, G ? xcc_id() : 0};
   for (int item; (item = next_item<G>(st, n_items, &a.counters[C_QUEUE_NH], &s_item)) >= 0;)
@@ -1202,25 +1323,62 @@ template <bool G>
 __global__ __launch_bounds__(kWG) void k_label(DescArg<G> dg, Geom g, Arena a) {
   const RunDesc d = dg.get();
   const bool fol = !(g.flags & 8u);
-  const int stride = gridDim.x * kWG;
-  for (int s = blockIdx.x * kWG + threadIdx.x; s < d.n; s += stride) {
-    const int p0 = a.parent[s];
-    if (fol && (a.flags[s] & F_FOLLOWER)) {
-      const int owner = a.hs[p0];
-      a.flist[a.fstart[owner] + a.frank[s]] = a.hs[s];
+  constexpr int U = kPlaceU;  // hits per lane per step, their chases interleaved
+  const int stride = gridDim.x * kWG * U;
+  for (int sb = blockIdx.x * kWG * U + (int)threadIdx.x; sb < d.n; sb += stride) {
+    int s[U], p0[U], hsj[U], r[U], p[U];
+    unsigned f[U];
+    bool v[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      s[j] = sb + j * kWG;
+      v[j] = s[j] < d.n;
+      p0[j] = s[j];
+      hsj[j] = 0;
+      f[j] = 0;
+      if (v[j]) {
+        p0[j] = a.parent[s[j]];
+        f[j] = a.flags[s[j]];
+        hsj[j] = a.hs[s[j]];
+      }
     }
-    int r = s, p = p0;
-    while (p != r) {
-      r = p;
-      p = ld_relaxed(&a.parent[r]);
+    if (fol) {
+#pragma unroll
+      for (int j = 0; j < U; ++j) {
+        if (v[j] && (f[j] & F_FOLLOWER)) {
+          const int owner = a.hs[p0[j]];
+          a.flist[a.fstart[owner] + a.frank[s[j]]] = hsj[j];
+        }
+      }
     }
-    if (r != s && r != p0) st_relaxed(&a.parent[s], r);
-    int lab = -1;
-    if (a.flags[r] & F_SEED) {
-      const int e = event_of_slot(g, a, d, s);
-      lab = a.seed_rank[a.hs[r]] - a.seed_rank[event_first_hit(a, d, e)];
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      r[j] = s[j];
+      p[j] = p0[j];
     }
-    d.cluster_id[a.hs[s]] = lab;
+    for (;;) {
+      bool more = false;
+#pragma unroll
+      for (int j = 0; j < U; ++j) {
+        if (p[j] != r[j]) {
+          r[j] = p[j];
+          p[j] = ld_relaxed(&a.parent[r[j]]);
+          more = true;
+        }
+      }
+      if (!more) break;
+    }
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      if (!v[j]) continue;
+      if (r[j] != s[j] && r[j] != p0[j]) st_relaxed(&a.parent[s[j]], r[j]);
+      int lab = -1;
+      if (a.flags[r[j]] & F_SEED) {
+        const int e = d.event ? clampi(d.event[hsj[j]] - d.event_base, 0, d.n_events - 1) : 0;
+        lab = a.seed_rank[a.hs[r[j]]] - a.seed_rank[event_first_hit(a, d, e)];
+      }
+      d.cluster_id[hsj[j]] = lab;
+    }
   }
 }
 
@@ -1228,22 +1386,37 @@ __global__ __launch_bounds__(kWG) void k_label(DescArg<G> dg, Geom g, Arena a) {
 template <bool G>
 __global__ __launch_bounds__(kWG) void k_follow_sort(DescArg<G> dg, Geom g, Arena a) {
   const RunDesc d = dg.get();
-  const int stride = gridDim.x * kWG;
-  for (int h = blockIdx.x * kWG + threadIdx.x; h < d.n; h += stride) {
-    const int b = a.fstart[h], end = a.fstart[h + 1];
-    if (b == end) continue;
-    for (int i = b + 1; i < end; ++i) {
-      const int v = a.flist[i];
-      int j = i - 1;
-      while (j >= b && a.flist[j] > v) {
-        a.flist[j + 1] = a.flist[j];
-        --j;
+  constexpr int U = kPlaceU;
+  const int stride = gridDim.x * kWG * U;
+  for (int hb = blockIdx.x * kWG * U + (int)threadIdx.x; hb < d.n; hb += stride) {
+    int b[U], end[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      const int h = hb + j * kWG;
+      b[j] = 0;
+      end[j] = 0;
+      if (h < d.n) {
+        b[j] = a.fstart[h];
+        end[j] = a.fstart[h + 1];
       }
-      a.flist[j + 1] = v;
     }
-    const int e = d.event ? clampi(d.event[h] - d.event_base, 0, d.n_events - 1) : 0;
-    const int off = event_first_hit(a, d, e);
-    for (int i = b; i < end; ++i) a.flist[i] -= off;
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      if (b[j] == end[j]) continue;
+      const int h = hb + j * kWG;
+      for (int i = b[j] + 1; i < end[j]; ++i) {
+        const int v = a.flist[i];
+        int k = i - 1;
+        while (k >= b[j] && a.flist[k] > v) {
+          a.flist[k + 1] = a.flist[k];
+          --k;
+        }
+        a.flist[k + 1] = v;
+      }
+      const int e = d.event ? clampi(d.event[h] - d.event_base, 0, d.n_events - 1) : 0;
+      const int off = event_first_hit(a, d, e);
+      for (int i = b[j]; i < end[j]; ++i) a.flist[i] -= off;
+    }
   }
 }
 
@@ -1271,11 +1444,13 @@ __global__ void k_set_desc(RunDesc d, RunDesc* dd) {
 // ---------------------------------------------------------------------------
 // Host launches.
 // ---------------------------------------------------------------------------
-// Dynamic LDS of the tile-block kernels: per staged hit a float4 record, an
-// int and a 16-bit tile id, plus four 16-bit quad-list entries.
-int lds_bytes_for(int lds_cap) { return lds_cap * (16 + 4 + 2 + 8); }
-// Nearest-higher: per staged hit a float4 record and one queue int.
-int lds_bytes_nh(int lds_cap) { return lds_cap * (16 + 4); }
+// Dynamic LDS of the density kernel: per staged hit a float4 record, a 16-bit
+// tile id and four 16-bit quad-list entries, then the region's tile offsets
+// and quad-list offsets.
+int lds_bytes_for(const Geom& g) { return lds_records_density(g.lds_cap) + 4 * (g.ts_ints + g.q_ints); }
+// Nearest-higher: per staged hit a float4 record and one queue int, then the
+// region's tile offsets.
+int lds_bytes_nh(const Geom& g) { return g.lds_cap * (16 + 4) + 4 * g.ts_ints; }
 
 static inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
@@ -1311,16 +1486,18 @@ static hipError_t launch_all(const Geom& g, const Arena& a, DescArg<G> dg, const
   mark();
   k_scatter<G><<<stream_grid(n), kWG, 0, s>>>(dg, g, a);
   mark();
-  const int lds = lds_bytes_for(g.lds_cap);
+  k_place<G><<<stream_grid(n), kWG, 0, s>>>(dg, g, a);
+  mark();
+  const int lds = lds_bytes_for(g);
   if (g.maxl == 2)
     k_density<G, 2><<<g_rho, kWG, lds, s>>>(dg, g, a);
   else
     k_density<G, 3><<<g_rho, kWG, lds, s>>>(dg, g, a);
   mark();
   if (g.flags & 4u)
-    k_nearest_higher<G, true><<<g_nh, kWG, lds_bytes_nh(g.lds_cap), s>>>(dg, g, a);
+    k_nearest_higher<G, true><<<g_nh, kWG, lds_bytes_nh(g), s>>>(dg, g, a);
   else
-    k_nearest_higher<G, false><<<g_nh, kWG, lds_bytes_nh(g.lds_cap), s>>>(dg, g, a);
+    k_nearest_higher<G, false><<<g_nh, kWG, lds_bytes_nh(g), s>>>(dg, g, a);
   mark();
   if (fol)
     k_scan<G, SCAN_SEEDS_FOLLOW><<<g_scan_s, kWG, 0, s>>>(dg, g, a);

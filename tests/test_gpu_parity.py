@@ -54,7 +54,9 @@ TUNINGS = [
     dict(threads_per_query=2),
     dict(threads_per_query=4, block_x=16, block_y=4),
     dict(threads_per_query=8),
-    dict(lds_cap=64),                         # blocks overflow LDS: per-tile regions, then global
+    dict(lds_cap=64),                         # blocks overflow LDS: quarters, single tiles, then global
+    dict(lds_cap=128),                        # quarter blocks fit where whole blocks do not
+    dict(lds_cap=96, block_x=4, block_y=4),
     dict(lds_cap=64, tile_size=2.5, threads_per_query=4),
     dict(nh_first_radius=0.0),                # single-phase nearest-higher search
     dict(nh_first_radius=0.5, threads_per_query=2),
