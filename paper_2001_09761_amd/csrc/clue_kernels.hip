@@ -757,28 +757,8 @@ __device__ __forceinline__ float density_global(const Geom& g, const Arena& a, i
   return acc;
 }
 
-// Records of the index-sorted list rec[lo, hi) whose hit index is below `k`:
-// a predicated linear count for short lists (independent loads), a binary
-// search otherwise.
+// Hit index of an LDS record.
 __device__ __forceinline__ int rec_key(const float4* rec, int j) { return __float_as_int(rec[j].w); }
-__device__ __forceinline__ int count_below(const float4* rec, int lo, int hi, int k) {
-  if (hi - lo <= 8) {
-    int c = 0;
-#pragma unroll
-    for (int j = 0; j < 8; ++j)
-      if (lo + j < hi) c += rec_key(rec, lo + j) < k;
-    return c;
-  }
-  const int base = lo;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (rec_key(rec, mid) < k)
-      lo = mid + 1;
-    else
-      hi = mid;
-  }
-  return lo - base;
-}
 
 // Density over a staged region (records x, y, E, index; each tile in
 // ascending hit index). With MAXL == 2 every query window lies inside the
@@ -866,11 +846,14 @@ __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, co
           const int ax = tc - dx, ay = tr - dy;
           qv[dy][dx] = ax >= qx0 && ax <= qx1 && ay >= qy0 && ay <= qy1;
         }
-      int below[3][3];
+      // lower bounds in the needed neighbour tiles, the (up to eight) binary
+      // searches advanced in lockstep so their LDS loads overlap
+      int lo[9], len[9];
 #pragma unroll
       for (int oy = -1; oy <= 1; ++oy)
 #pragma unroll
         for (int ox = -1; ox <= 1; ++ox) {
+          const int k = (oy + 1) * 3 + ox + 1;
           bool need = false;
 #pragma unroll
           for (int dy = 0; dy < 2; ++dy)
@@ -879,13 +862,36 @@ __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, co
               need |= qv[dy][dx] && (ox == -dx || ox == 1 - dx) && (oy == -dy || oy == 1 - dy);
           const int nx = tc + ox, ny = tr + oy;
           need &= (ox != 0 || oy != 0) && nx >= 0 && nx < R.rw && ny >= 0 && ny < R.rh;
-          int c = 0;
+          lo[k] = 0;
+          len[k] = 0;
           if (need) {
             const int nt = ny * per_row + nx;
-            c = count_below(rec, L.ts[nt], L.ts[nt + 1], hp);
+            lo[k] = L.ts[nt];
+            len[k] = L.ts[nt + 1] - lo[k];
           }
-          below[oy + 1][ox + 1] = c;
         }
+      int below[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) below[k] = lo[k];
+      for (;;) {
+        bool more = false;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+          if (len[k] > 0) {
+            more = true;
+            const int half = len[k] >> 1;
+            if (rec_key(rec, below[k] + half) < hp) {
+              below[k] += half + 1;
+              len[k] -= half + 1;
+            } else {
+              len[k] = half;
+            }
+          }
+        }
+        if (!more) break;
+      }
+#pragma unroll
+      for (int k = 0; k < 9; ++k) below[k] -= lo[k];
 #pragma unroll
       for (int dy = 0; dy < 2; ++dy)
 #pragma unroll
@@ -896,7 +902,7 @@ __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, co
           for (int oy = -dy; oy <= 1 - dy; ++oy)
 #pragma unroll
             for (int ox = -dx; ox <= 1 - dx; ++ox)
-              if (ox != 0 || oy != 0) pos += below[oy + 1][ox + 1];
+              if (ox != 0 || oy != 0) pos += below[(oy + 1) * 3 + ox + 1];
           qidx[L.qoff[(tr - dy - qy0) * qw + (tc - dx - qx0)] + pos] = (unsigned short)p;
         }
     }
@@ -1102,12 +1108,12 @@ __device__ __forceinline__ void decide_and_store(const Geom& g, const Arena& a, 
 // Scans window tiles [tx0..tx1] x [ty0..ty1] (region coordinates) of the
 // staged records (x, y, ord(rho), index) with lanes sub, sub + step, ...
 template <bool STRICT>
-__device__ __forceinline__ void nh_scan_staged(const float4* __restrict__ rec, const RegionLds& L, int per_row,
+__device__ __forceinline__ void nh_scan_staged(const float4* __restrict__ rec, const int* ts, int per_row,
                                                int tx0, int tx1, int ty0, int ty1, int sub, int step, float xi,
                                                float yi, unsigned ordi, unsigned hi, float thr, NhBest& b) {
   for (int ty = ty0; ty <= ty1; ++ty) {
-    const int q0 = L.ts[ty * per_row + tx0];
-    const int q1 = L.ts[ty * per_row + tx1 + 1];
+    const int q0 = ts[ty * per_row + tx0];
+    const int q1 = ts[ty * per_row + tx1 + 1];
     int c = q0 + sub;
     // four independent LDS loads in flight per step
     for (; c + 3 * step < q1; c += 4 * step) {
@@ -1177,7 +1183,7 @@ __device__ __forceinline__ void nh_staged(const Geom& g, const Arena& a, const R
       const int tx0 = W.x0 - R.rx0, tx1 = W.x1 - R.rx0, ty0 = W.y0 - R.ry0, ty1 = W.y1 - R.ry0;
       if (tx0 >= 0 && ty0 >= 0 && tx1 < R.rw && ty1 < R.rh) {
         NhBest b{~0ull, -1};
-        nh_scan_staged<STRICT>(rec, L, per_row, tx0, tx1, ty0, ty1, 0, 1, me.x, me.y, ordi, hi, g.r1sq, b);
+        nh_scan_staged<STRICT>(rec, L.ts, per_row, tx0, tx1, ty0, ty1, 0, 1, me.x, me.y, ordi, hi, g.r1sq, b);
         if (b.p >= 0) {
           b.p = slot_of(L, region_row_of(L, R.rh, b.p), b.p);
           decide_and_store(g, a, d, slot_of(L, row, p), (int)hi, ord_inv(ordi), b, ev_first);
@@ -1209,7 +1215,7 @@ __device__ __forceinline__ void nh_staged(const Geom& g, const Arena& a, const R
       const Window W = query_window(g, g.win_dm, me.x, me.y);
       const int tx0 = W.x0 - R.rx0, tx1 = W.x1 - R.rx0, ty0 = W.y0 - R.ry0, ty1 = W.y1 - R.ry0;
       if (tx0 >= 0 && ty0 >= 0 && tx1 < R.rw && ty1 < R.rh) {
-        nh_scan_staged<STRICT>(rec, L, per_row, tx0, tx1, ty0, ty1, sub, tpq, me.x, me.y, ordi, hi, g.dm2, b);
+        nh_scan_staged<STRICT>(rec, L.ts, per_row, tx0, tx1, ty0, ty1, sub, tpq, me.x, me.y, ordi, hi, g.dm2, b);
       } else {
         atomicOr(a.err, (uint32_t)E_WINDOW);
         nh_global_scan<STRICT>(g, a, ubase, W, sub, tpq, me.x, me.y, ordi, hi, b);
@@ -1258,8 +1264,8 @@ __device__ __forceinline__ void nh_global_region(const Geom& g, const Arena& a, 
 }
 
 template <bool STRICT>
-__device__ __forceinline__ void nh_item(const Geom& g, const Arena& a, const RunDesc& d, int item, RegionLds& L, float4* rec,
-                        int* queue, int* s_qn) {
+__device__ __forceinline__ void nh_item(const Geom& g, const Arena& a, const RunDesc& d, int item, RegionLds& L,
+                                        float4* rec, int* queue, int* s_qn) {
   int unit, tx0, ty0, tx1, ty1;
   item_block(g, item, unit, tx0, ty0, tx1, ty1);
   Region R;
