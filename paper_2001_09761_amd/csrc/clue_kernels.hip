@@ -115,53 +115,69 @@ __global__ __launch_bounds__(kWG) void k_clear(DescArg<G> dg, Geom g, Arena a) {
 // k_hist: tile of every hit, atomic count per tile, arrival rank kept.
 // Lanes of a wave that share a tile are grouped first, so each distinct tile
 // costs one atomic per wave (hits of a cluster tend to be adjacent in input
-// order); ranks within a group follow lane order.
+// order); ranks within a group follow lane order. Each lane takes kPlaceU
+// hits per step so that their atomics are in flight together.
 // ---------------------------------------------------------------------------
 template <bool G>
 __global__ __launch_bounds__(kWG) void k_hist(DescArg<G> dg, Geom g, Arena a) {
   const RunDesc d = dg.get();
-  const int stride = gridDim.x * kWG;
+  constexpr int U = kPlaceU;  // sub-batches per step; their atomics overlap
+  const int stride = gridDim.x * kWG * U;
   const int lane = threadIdx.x & 63;
-  for (int h0 = blockIdx.x * kWG; h0 < d.n; h0 += stride) {  // uniform per workgroup
-    const int h = h0 + (int)threadIdx.x;
-    const bool valid = h < d.n;
-    int t = -1;
-    if (valid) {
-      int e = 0;
-      if (d.event) {
-        e = clampi(d.event[h] - d.event_base, 0, d.n_events - 1);
-        const int prev = h == 0 ? -1 : clampi(d.event[h - 1] - d.event_base, 0, d.n_events - 1);
-        for (int k = prev + 1; k <= e; ++k) a.ev_start[k] = h;
-        if (h == d.n - 1)
-          for (int k = e + 1; k <= d.n_events; ++k) a.ev_start[k] = d.n;
-      } else if (h == 0) {
-        a.ev_start[0] = 0;
-        a.ev_start[1] = d.n;
+  for (int h0 = blockIdx.x * kWG * U; h0 < d.n; h0 += stride) {  // uniform per workgroup
+    int t[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      const int h = h0 + j * kWG + (int)threadIdx.x;
+      t[j] = -1;
+      if (h < d.n) {
+        int e = 0;
+        if (d.event) {
+          e = clampi(d.event[h] - d.event_base, 0, d.n_events - 1);
+          const int prev = h == 0 ? -1 : clampi(d.event[h - 1] - d.event_base, 0, d.n_events - 1);
+          for (int k = prev + 1; k <= e; ++k) a.ev_start[k] = h;
+          if (h == d.n - 1)
+            for (int k = e + 1; k <= d.n_events; ++k) a.ev_start[k] = d.n;
+        } else if (h == 0) {
+          a.ev_start[0] = 0;
+          a.ev_start[1] = d.n;
+        }
+        const int l = clampi(d.layer[h], 0, g.L - 1);
+        const int tx = tile_coord(d.x[h], g.x0, g.inv_t, g.nx);
+        const int ty = tile_coord(d.y[h], g.y0, g.inv_t, g.ny);
+        t[j] = (e * g.L + l) * g.tpl + ty * g.nx + tx;
       }
-      const int l = clampi(d.layer[h], 0, g.L - 1);
-      const int tx = tile_coord(d.x[h], g.x0, g.inv_t, g.nx);
-      const int ty = tile_coord(d.y[h], g.y0, g.inv_t, g.ny);
-      t = (e * g.L + l) * g.tpl + ty * g.nx + tx;
     }
-    unsigned long long todo = __ballot(valid);
-    int leader = lane, off = 0, cnt = 0;
-    while (todo) {  // wave-uniform: one pass per distinct tile in the wave
-      const int l = __ffsll((long long)todo) - 1;
-      const int lt = __shfl(t, l, 64);
-      const unsigned long long peers = __ballot(t == lt) & todo;
-      if ((peers >> lane) & 1ull) {
-        leader = l;
-        off = __popcll(peers & ((1ull << lane) - 1ull));
+    int base[U], off[U], leader[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      const bool valid = t[j] >= 0;
+      unsigned long long todo = __ballot(valid);
+      int ld = lane, o = 0, cnt = 0;
+      while (todo) {  // wave-uniform: one pass per distinct tile in the wave
+        const int l = __ffsll((long long)todo) - 1;
+        const int lt = __shfl(t[j], l, 64);
+        const unsigned long long peers = __ballot(t[j] == lt) & todo;
+        if ((peers >> lane) & 1ull) {
+          ld = l;
+          o = __popcll(peers & ((1ull << lane) - 1ull));
+        }
+        if (lane == l) cnt = __popcll(peers);
+        todo &= ~peers;
       }
-      if (lane == l) cnt = __popcll(peers);
-      todo &= ~peers;
+      base[j] = 0;
+      if (valid && lane == ld) base[j] = atomicAdd(&a.tile_start[t[j]], cnt);
+      off[j] = o;
+      leader[j] = ld;
     }
-    int base = 0;
-    if (valid && lane == leader) base = atomicAdd(&a.tile_start[t], cnt);
-    base = __shfl(base, leader, 64);
-    if (valid) {
-      a.key[h] = t;
-      a.rank[h] = base + off;
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      const int bs = __shfl(base[j], leader[j], 64);
+      const int h = h0 + j * kWG + (int)threadIdx.x;
+      if (t[j] >= 0) {
+        a.key[h] = t[j];
+        a.rank[h] = bs + off[j];
+      }
     }
   }
 }
@@ -179,12 +195,27 @@ template <bool G>
 __global__ __launch_bounds__(kWG) void k_scatter(DescArg<G> dg, Geom g, Arena a) {
   const RunDesc d = dg.get();
   int* ids = reinterpret_cast<int*>(a.rho);
-  const int stride = gridDim.x * kWG;
-  for (int h = blockIdx.x * kWG + threadIdx.x; h < d.n; h += stride) {
-    const int t = a.key[h];
-    const int s = a.tile_start[t] + a.rank[h];
-    ids[s] = h;
-    a.parent[s] = t;
+  constexpr int U = kPlaceU;
+  const int stride = gridDim.x * kWG * U;
+  for (int h0 = blockIdx.x * kWG * U + (int)threadIdx.x; h0 < d.n; h0 += stride) {
+    int t[U], r[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      const int h = h0 + j * kWG;
+      t[j] = -1;
+      if (h < d.n) {
+        t[j] = a.key[h];
+        r[j] = a.rank[h];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      if (t[j] >= 0) {
+        const int s = a.tile_start[t[j]] + r[j];
+        ids[s] = h0 + j * kWG;
+        a.parent[s] = t[j];
+      }
+    }
   }
 }
 
@@ -1389,6 +1420,10 @@ __global__ __launch_bounds__(kWG) void k_label(DescArg<G> dg, Geom g, Arena a) {
 }
 
 // Follower lists: sort each list by hit index, then make indices event-local.
+// Lists of up to kShortList entries are sorted in registers (an odd-even
+// transposition network); longer ones by insertion in place.
+constexpr int kShortList = 8;
+
 template <bool G>
 __global__ __launch_bounds__(kWG) void k_follow_sort(DescArg<G> dg, Geom g, Arena a) {
   const RunDesc d = dg.get();
@@ -1408,8 +1443,28 @@ __global__ __launch_bounds__(kWG) void k_follow_sort(DescArg<G> dg, Geom g, Aren
     }
 #pragma unroll
     for (int j = 0; j < U; ++j) {
-      if (b[j] == end[j]) continue;
+      const int len = end[j] - b[j];
+      if (len == 0) continue;
       const int h = hb + j * kWG;
+      const int e = d.event ? clampi(d.event[h] - d.event_base, 0, d.n_events - 1) : 0;
+      const int off = event_first_hit(a, d, e);
+      if (len <= kShortList) {
+        int v[kShortList];
+#pragma unroll
+        for (int i = 0; i < kShortList; ++i) v[i] = i < len ? a.flist[b[j] + i] : INT_MAX;
+#pragma unroll
+        for (int r = 0; r < kShortList; ++r)
+#pragma unroll
+          for (int i = r & 1; i + 1 < kShortList; i += 2) {
+            const int lo = min(v[i], v[i + 1]), hi = max(v[i], v[i + 1]);
+            v[i] = lo;
+            v[i + 1] = hi;
+          }
+#pragma unroll
+        for (int i = 0; i < kShortList; ++i)
+          if (i < len) a.flist[b[j] + i] = v[i] - off;
+        continue;
+      }
       for (int i = b[j] + 1; i < end[j]; ++i) {
         const int v = a.flist[i];
         int k = i - 1;
@@ -1419,8 +1474,6 @@ __global__ __launch_bounds__(kWG) void k_follow_sort(DescArg<G> dg, Geom g, Aren
         }
         a.flist[k + 1] = v;
       }
-      const int e = d.event ? clampi(d.event[h] - d.event_base, 0, d.n_events - 1) : 0;
-      const int off = event_first_hit(a, d, e);
       for (int i = b[j]; i < end[j]; ++i) a.flist[i] -= off;
     }
   }
@@ -1486,11 +1539,11 @@ static hipError_t launch_all(const Geom& g, const Arena& a, DescArg<G> dg, const
   mark();
   k_clear<G><<<g_clear, kWG, 0, s>>>(dg, g, a);
   mark();
-  k_hist<G><<<stream_grid(n), kWG, 0, s>>>(dg, g, a);
+  k_hist<G><<<stream_grid(cdiv(n, kPlaceU)), kWG, 0, s>>>(dg, g, a);
   mark();
   k_scan<G, SCAN_TILES><<<g_scan_t, kWG, 0, s>>>(dg, g, a);
   mark();
-  k_scatter<G><<<stream_grid(n), kWG, 0, s>>>(dg, g, a);
+  k_scatter<G><<<stream_grid(cdiv(n, kPlaceU)), kWG, 0, s>>>(dg, g, a);
   mark();
   k_place<G><<<stream_grid(n), kWG, 0, s>>>(dg, g, a);
   mark();
@@ -1510,9 +1563,9 @@ static hipError_t launch_all(const Geom& g, const Arena& a, DescArg<G> dg, const
   else
     k_scan<G, SCAN_SEEDS><<<g_scan_s, kWG, 0, s>>>(dg, g, a);
   mark();
-  k_label<G><<<stream_grid(n), kWG, 0, s>>>(dg, g, a);
+  k_label<G><<<stream_grid(cdiv(n, kPlaceU)), kWG, 0, s>>>(dg, g, a);
   mark();
-  if (fol) k_follow_sort<G><<<stream_grid(n), kWG, 0, s>>>(dg, g, a);
+  if (fol) k_follow_sort<G><<<stream_grid(cdiv(n, kPlaceU)), kWG, 0, s>>>(dg, g, a);
   mark();
   return hipGetLastError();
 }
