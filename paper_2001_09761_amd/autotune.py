@@ -2,7 +2,8 @@
 
 Sweeps the kernel tuning (tile size, tile-block shape, LDS budget, lanes per
 full-window nearest-higher query, first nearest-higher radius and the density
-strategy) by coordinate descent on a sample batch, timing each candidate
+strategy) by coordinate descent on a sample batch (repeated from the best
+point while a sweep improves it, up to `sweeps` times), timing each candidate
 with HIP events on the run's stream. Every candidate must reproduce the
 reference cluster ids and seed flags bit for bit, or the tuner raises: the
 tuning may change speed only. The winner is cached as JSON, keyed by GPU
@@ -34,6 +35,20 @@ def default_space(params):
         ("tile_size", [base_t, base_t * 1.25, base_t * 1.5]),
         ("nh_first_radius", [0.25 * dm, 0.375 * dm, 0.5 * dm, 0.0]),
         ("threads_per_query", [1, 2, 4]),
+    ]
+
+
+def default_seeds(params):
+    """Starting points besides the context's current tuning (coordinate
+    descent from one point can stop in a local optimum)."""
+    dc = float(params["dc"])
+    dm = max(float(params["delta_c"]), float(params["delta_o"]))
+    base_t = max(dm, 2.0 * dc) * (1.0 + 1.0 / 128.0)
+    return [
+        dict(tile_size=base_t * 1.25, block=(8, 8), lds_cap=960, nh_first_radius=0.375 * dm, threads_per_query=4,
+             density_quads=1),
+        dict(tile_size=base_t, block=(16, 8), lds_cap=1024, nh_first_radius=0.0, threads_per_query=1,
+             density_quads=1),
     ]
 
 
@@ -80,7 +95,8 @@ def _apply(ctx, t):
                    lds_cap=t["lds_cap"], nh_first_radius=t["nh_first_radius"], density_quads=t["density_quads"])
 
 
-def autotune(ctx, batch, n_events, params, *, reps=3, space=None, stage_times=False, log=print):
+def autotune(ctx, batch, n_events, params, *, reps=3, space=None, stage_times=False, log=print, sweeps=2,
+             seeds=None):
     """Tunes ``ctx`` on ``batch`` (dict of device tensors event, x, y, layer,
     energy) and leaves the best tuning applied. Returns (best, table)."""
     import torch
@@ -130,20 +146,44 @@ def autotune(ctx, batch, n_events, params, *, reps=3, space=None, stage_times=Fa
 
     best_ms, st = measure(best)
     table.append(dict(best, ms=best_ms, stages=st))
-    for axis, values in (space or default_space(params)):
-        for v in values:
-            t = dict(best)
-            t[axis] = v
-            if t == best:
-                continue
-            ms, st = measure(t)
-            table.append(dict(t, ms=ms, stages=st))
-            if log:
-                log(f"autotune {axis}={v}: {ms if ms is None else round(ms, 4)} ms")
-            if ms is not None and ms < best_ms:
-                best, best_ms = t, ms
+    tried = {_freeze(best)}
+    # other starting points: the descent keeps the best of all of them
+    for sd in (default_seeds(params) if seeds is None else seeds):
+        t = dict(best)
+        t.update(sd)
+        if _freeze(t) in tried:
+            continue
+        tried.add(_freeze(t))
+        ms, st = measure(t)
+        table.append(dict(t, ms=ms, stages=st))
+        if log:
+            log(f"autotune seed {sd}: {ms if ms is None else round(ms, 4)} ms")
+        if ms is not None and ms < best_ms:
+            best, best_ms = t, ms
+    for sweep in range(sweeps):  # coordinate descent, repeated while it improves
+        improved = False
+        for axis, values in (space or default_space(params)):
+            for v in values:
+                t = dict(best)
+                t[axis] = v
+                if _freeze(t) in tried:
+                    continue
+                tried.add(_freeze(t))
+                ms, st = measure(t)
+                table.append(dict(t, ms=ms, stages=st))
+                if log:
+                    log(f"autotune sweep {sweep} {axis}={v}: {ms if ms is None else round(ms, 4)} ms")
+                if ms is not None and ms < best_ms:
+                    best, best_ms = t, ms
+                    improved = True
+        if not improved:
+            break
     _apply(ctx, best)
     return dict(best, ms=best_ms), table
+
+
+def _freeze(t):
+    return tuple(sorted((k, tuple(v) if isinstance(v, (list, tuple)) else v) for k, v in t.items()))
 
 
 def tuned_context_setup(ctx, batch, n_events, params, *, cache_path=DEFAULT_CACHE, reps=3, log=None):
@@ -177,7 +217,7 @@ def _main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", choices=["cfg2", "cfg4"], default="cfg2")
     ap.add_argument("--events", type=int, default=32)
-    ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--out", default=DEFAULT_CACHE)
     args = ap.parse_args()
     dev = torch.device("cuda", 0)
