@@ -30,9 +30,10 @@ def default_space(params):
     base_t = max(dm, 2.0 * dc) * (1.0 + 1.0 / 128.0)
     return [
         ("density_quads", [1, 2]),
-        ("block", [(8, 8), (8, 4), (16, 8), (4, 4), (16, 16)]),
-        ("lds_cap", [960, 1024, 768, 2048, 512]),
-        ("tile_size", [base_t, base_t * 1.25, base_t * 1.5]),
+        ("block", [(8, 8), (10, 10), (12, 12), (10, 8), (12, 8), (9, 9), (11, 11), (16, 8), (8, 4), (4, 4),
+                   (16, 16)]),
+        ("lds_cap", [960, 1024, 896, 768, 2048, 512]),
+        ("tile_size", [base_t, base_t * 1.125, base_t * 1.25, base_t * 1.5]),
         ("nh_first_radius", [0.25 * dm, 0.375 * dm, 0.5 * dm, 0.0]),
         ("threads_per_query", [1, 2, 4]),
     ]
@@ -45,6 +46,8 @@ def default_seeds(params):
     dm = max(float(params["delta_c"]), float(params["delta_o"]))
     base_t = max(dm, 2.0 * dc) * (1.0 + 1.0 / 128.0)
     return [
+        dict(tile_size=base_t, block=(10, 10), lds_cap=960, nh_first_radius=0.375 * dm, threads_per_query=4,
+             density_quads=1),
         dict(tile_size=base_t * 1.25, block=(8, 8), lds_cap=960, nh_first_radius=0.375 * dm, threads_per_query=4,
              density_quads=1),
         dict(tile_size=base_t, block=(16, 8), lds_cap=1024, nh_first_radius=0.0, threads_per_query=1,
