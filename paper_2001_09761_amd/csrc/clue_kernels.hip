@@ -1070,7 +1070,8 @@ __global__ __launch_bounds__(kWG) void k_density(DescArg<G> dg, Geom g, Arena a)
 // higher hit lies strictly within r1, no hit outside that window can be
 // closer, so the query is done. Other queries are queued in LDS and searched
 // over the full d_m window with `tpq` lanes each (phase 2).
-// Records: (x, y, rho, hit index as bits).
+// Records: (x, y, hit index as bits, ord(rho)); the last two halves form
+// the 64-bit (ord(rho), index) key in register order.
 // ---------------------------------------------------------------------------
 // Order-preserving map of a float to uint32 (-0 folds onto +0), so that
 // (rho, index) compares as one 64-bit unsigned key.
@@ -1137,7 +1138,7 @@ __device__ __forceinline__ void decide_and_store(const Geom& g, const Arena& a, 
 }
 
 // Scans window tiles [tx0..tx1] x [ty0..ty1] (region coordinates) of the
-// staged records (x, y, ord(rho), index) with lanes sub, sub + step, ...
+// staged records (x, y, index, ord(rho)) with lanes sub, sub + step, ...
 template <bool STRICT>
 __device__ __forceinline__ void nh_scan_staged(const float4* __restrict__ rec, const int* ts, int per_row,
                                                int tx0, int tx1, int ty0, int ty1, int sub, int step, float xi,
@@ -1149,18 +1150,18 @@ __device__ __forceinline__ void nh_scan_staged(const float4* __restrict__ rec, c
     // four independent LDS loads in flight per step
     for (; c + 3 * step < q1; c += 4 * step) {
       const float4 r0 = rec[c], r1 = rec[c + step], r2 = rec[c + 2 * step], r3 = rec[c + 3 * step];
-      nh_consider<STRICT>(b, dist2(xi, yi, r0.x, r0.y), __float_as_uint(r0.z), __float_as_uint(r0.w), c, ordi, hi,
+      nh_consider<STRICT>(b, dist2(xi, yi, r0.x, r0.y), __float_as_uint(r0.w), __float_as_uint(r0.z), c, ordi, hi,
                           thr);
-      nh_consider<STRICT>(b, dist2(xi, yi, r1.x, r1.y), __float_as_uint(r1.z), __float_as_uint(r1.w), c + step,
+      nh_consider<STRICT>(b, dist2(xi, yi, r1.x, r1.y), __float_as_uint(r1.w), __float_as_uint(r1.z), c + step,
                           ordi, hi, thr);
-      nh_consider<STRICT>(b, dist2(xi, yi, r2.x, r2.y), __float_as_uint(r2.z), __float_as_uint(r2.w),
+      nh_consider<STRICT>(b, dist2(xi, yi, r2.x, r2.y), __float_as_uint(r2.w), __float_as_uint(r2.z),
                           c + 2 * step, ordi, hi, thr);
-      nh_consider<STRICT>(b, dist2(xi, yi, r3.x, r3.y), __float_as_uint(r3.z), __float_as_uint(r3.w),
+      nh_consider<STRICT>(b, dist2(xi, yi, r3.x, r3.y), __float_as_uint(r3.w), __float_as_uint(r3.z),
                           c + 3 * step, ordi, hi, thr);
     }
     for (; c < q1; c += step) {
       const float4 r = rec[c];
-      nh_consider<STRICT>(b, dist2(xi, yi, r.x, r.y), __float_as_uint(r.z), __float_as_uint(r.w), c, ordi, hi, thr);
+      nh_consider<STRICT>(b, dist2(xi, yi, r.x, r.y), __float_as_uint(r.w), __float_as_uint(r.z), c, ordi, hi, thr);
     }
   }
 }
@@ -1196,7 +1197,7 @@ __device__ __forceinline__ void nh_staged(const Geom& g, const Arena& a, const R
 #pragma unroll
     for (int k = 0; k < kStagePer; ++k) {
       const int p = base + (int)threadIdx.x + k * kWG;
-      if (p < R.total) rec[p] = make_float4(v[k].x, v[k].y, __uint_as_float(ord_f32(v[k].z)), v[k].w);
+      if (p < R.total) rec[p] = make_float4(v[k].x, v[k].y, v[k].w, __uint_as_float(ord_f32(v[k].z)));
     }
   }
   if (threadIdx.x == 0) *s_qn = 0;
@@ -1209,7 +1210,7 @@ __device__ __forceinline__ void nh_staged(const Geom& g, const Arena& a, const R
       int row, p;
       core_query(L, R, q, row, p);
       const float4 me = rec[p];
-      const unsigned ordi = __float_as_uint(me.z), hi = __float_as_uint(me.w);
+      const unsigned ordi = __float_as_uint(me.w), hi = __float_as_uint(me.z);
       const Window W = query_window(g, g.win_r1, me.x, me.y);
       const int tx0 = W.x0 - R.rx0, tx1 = W.x1 - R.rx0, ty0 = W.y0 - R.ry0, ty1 = W.y1 - R.ry0;
       if (tx0 >= 0 && ty0 >= 0 && tx1 < R.rw && ty1 < R.rh) {
@@ -1241,8 +1242,8 @@ __device__ __forceinline__ void nh_staged(const Geom& g, const Arena& a, const R
       core_query(L, R, queue[qi], row, p);
       slot = slot_of(L, row, p);
       const float4 me = rec[p];
-      ordi = __float_as_uint(me.z);
-      hi = __float_as_uint(me.w);
+      ordi = __float_as_uint(me.w);
+      hi = __float_as_uint(me.z);
       const Window W = query_window(g, g.win_dm, me.x, me.y);
       const int tx0 = W.x0 - R.rx0, tx1 = W.x1 - R.rx0, ty0 = W.y0 - R.ry0, ty1 = W.y1 - R.ry0;
       if (tx0 >= 0 && ty0 >= 0 && tx1 < R.rw && ty1 < R.rh) {
