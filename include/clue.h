@@ -171,9 +171,11 @@ typedef struct {
   float nh_first_radius;    /* radius (cm) of the first nearest-higher pass; a hit
                                whose nearest-higher lies strictly inside it skips
                                the full d_m search. 0 or >= d_m: single pass */
-  int32_t density_quads;    /* 1: merge each 2x2-tile quad once per work item and
-                               scan it per hit; 2: each hit merges its own window
-                               lists; <= 0 keep */
+  int32_t density_quads;    /* 1: merge each 2x2-tile quad once per work item
+                               (element ranks by binary search) and scan it per
+                               hit; 2: each hit merges its own window lists;
+                               3: as 1, one lane merging each quad in order;
+                               <= 0 keep */
 } clue_tuning;
 
 /* Replace the tuning. Fields <= 0 keep their current value, except

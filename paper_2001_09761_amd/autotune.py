@@ -29,7 +29,7 @@ def default_space(params):
     dm = max(float(params["delta_c"]), float(params["delta_o"]))
     base_t = max(dm, 2.0 * dc) * (1.0 + 1.0 / 128.0)
     return [
-        ("density_quads", [1, 2]),
+        ("density_quads", [1, 3, 2]),
         ("block", [(8, 8), (10, 10), (12, 12), (10, 8), (12, 8), (9, 9), (11, 11), (16, 8), (8, 4), (4, 4),
                    (16, 16)]),
         ("lds_cap", [960, 1024, 896, 768, 2048, 512]),

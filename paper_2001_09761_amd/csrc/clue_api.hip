@@ -24,7 +24,7 @@ struct clue_ctx {
   float tile = 0.0f;
   int tpq = 1, bx = 8, by = 8, lds_cap = kDefaultLdsCap;
   float r1 = -1.0f;  // nearest-higher first radius; negative: default d_m / 4
-  int quads = 1;      // density strategy (1 quads, 2 per-query merge)
+  int quads = 1;      // density strategy (1 quads by search, 2 per-query merge, 3 quads by merge)
   LaunchCfg cfg{};
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -121,7 +121,7 @@ static int plan_geom(const clue_params& p, float tile, int tpq, int bx, int by, 
   g.win_dc = (float)((double)p.dc * (1.0 + 1.0 / 1024.0));
   g.win_dm = (float)((double)dm * (1.0 + 1.0 / 1024.0));
   g.flags = p.flags;
-  g.density_quads = quads == 2 ? 0 : 1;
+  g.density_quads = quads == 2 ? 0 : (quads == 3 ? 2 : 1);
   // First nearest-higher pass: radius r1 (default d_m / 4); off when r1 <= 0
   // or r1 >= d_m.
   const float r1v = r1 < 0.0f ? 0.25f * dm : r1;
@@ -597,7 +597,7 @@ int clue_get_tuning(const clue_ctx* c, clue_tuning* t, int32_t* halo) {
     t->block_y = c->g.by;
     t->lds_cap = c->g.lds_cap;
     t->nh_first_radius = c->g.nh_phase1 ? std::sqrt(c->g.r1sq) : 0.0f;
-    t->density_quads = c->g.density_quads ? 1 : 2;
+    t->density_quads = c->g.density_quads == 0 ? 2 : (c->g.density_quads == 2 ? 3 : 1);
   }
   if (halo) *halo = c->g.halo;
   return CLUE_OK;

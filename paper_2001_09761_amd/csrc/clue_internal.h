@@ -76,7 +76,7 @@ struct Geom {
   float rho_c;
   float win_dc;     // dc (1 + 2^-10): density window half width before the |x| margin
   float win_dm;     // dm (1 + 2^-10)
-  int32_t density_quads;  // 1: per-item merged quad lists; 0: per-query merge
+  int32_t density_quads;  // 1: per-item quad lists by search; 2: by sequential merge; 0: per-query merge
   int32_t nh_phase1;  // nearest-higher first searches radius r1 < dm
   float r1sq;       // fl(r1*r1)
   float win_r1;     // r1 (1 + 2^-10)

@@ -859,7 +859,44 @@ __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, co
     }
   }
   __syncthreads();
-  if (use_quads && *L.qtotal <= 4 * g.lds_cap) {
+  if (use_quads && *L.qtotal <= 4 * g.lds_cap && g.density_quads == 2) {
+    // one lane per quad: a sequential merge of its (up to four) index-sorted
+    // tile lists
+    for (int q = threadIdx.x; q < nquad; q += kWG) {
+      const int ax = qx0 + q % qw, ay = qy0 + q / qw;
+      const int bx1 = min(ax + 1, R.rw - 1), by1 = min(ay + 1, R.rh - 1);
+      int cur[4], end[4], key[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int tx = (k & 1) ? bx1 : ax, ty = (k & 2) ? by1 : ay;
+        const bool dup = ((k & 1) && bx1 == ax) || ((k & 2) && by1 == ay);
+        const int t = ty * per_row + tx;
+        cur[k] = dup ? 0 : L.ts[t];
+        end[k] = dup ? 0 : L.ts[t + 1];
+        key[k] = cur[k] < end[k] ? rec_key(rec, cur[k]) : INT_MAX;
+      }
+      const int out = L.qoff[q], n = L.qoff[q + 1] - out;
+      for (int i = 0; i < n; ++i) {
+        const int m = min(min(key[0], key[1]), min(key[2], key[3]));
+        const bool s0 = key[0] == m, s1 = !s0 && key[1] == m, s2 = !s0 && !s1 && key[2] == m;
+        const int pk = s0 ? cur[0] : (s1 ? cur[1] : (s2 ? cur[2] : cur[3]));
+        const int ek = s0 ? end[0] : (s1 ? end[1] : (s2 ? end[2] : end[3]));
+        qidx[out + i] = (unsigned short)pk;
+        const int np = pk + 1;
+        const int nk = np < ek ? rec_key(rec, np) : INT_MAX;
+        const bool s3 = !s0 && !s1 && !s2;
+        cur[0] = s0 ? np : cur[0];
+        key[0] = s0 ? nk : key[0];
+        cur[1] = s1 ? np : cur[1];
+        key[1] = s1 ? nk : key[1];
+        cur[2] = s2 ? np : cur[2];
+        key[2] = s2 ? nk : key[2];
+        cur[3] = s3 ? np : cur[3];
+        key[3] = s3 ? nk : key[3];
+      }
+    }
+    __syncthreads();
+  } else if (use_quads && *L.qtotal <= 4 * g.lds_cap) {
     // place every sorted record into each quad that holds its tile: its
     // position there is its rank in its own tile plus, for each other tile
     // of the quad, the entries with a smaller hit index (each of the up to

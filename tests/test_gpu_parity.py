@@ -58,6 +58,9 @@ TUNINGS = [
     dict(lds_cap=128),                        # quarter blocks fit where whole blocks do not
     dict(lds_cap=96, block_x=4, block_y=4),
     dict(lds_cap=64, tile_size=2.5, threads_per_query=4),
+    dict(density_quads=3),                    # quad lists merged by one lane each
+    dict(density_quads=3, tile_size=8.0, block_x=2, block_y=2, lds_cap=128),
+    dict(density_quads=2),                    # per-query merges, no quad lists
     dict(nh_first_radius=0.0),                # single-phase nearest-higher search
     dict(nh_first_radius=0.5, threads_per_query=2),
     dict(nh_first_radius=3.99),
