@@ -100,6 +100,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-extras", action="store_true", help="headline only (no 64-event or served runs)")
     ap.add_argument("--serve-rate", type=float, default=2000.0, help="offered events/s of the served stream")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the served-rate sweep (100 to 5000 events/s)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB device copy (HBM counter calibration)")
     ap.add_argument("--traffic-summary", metavar="DIR",
@@ -363,13 +364,25 @@ def extras(args, params, log):
                         tuning={k: v for k, v in dict(tuning).items() if k in ("tile_size", "threads_per_query",
                                                                              "lds_cap", "nh_first_radius",
                                                                              "density_quads")})
-    arrivals = gen.poisson_arrivals(args.serve_rate, len(pool_events))
-    sch = Scheduler(be, hbm_budget_bytes=64 << 30, max_batch_hits=cap, max_batch_events=8)
-    st = sch.run(arrivals, n_hits)
-    s = st.summary()
+    def served(rate):
+        arrivals = gen.poisson_arrivals(rate, len(pool_events))
+        sch = Scheduler(be, hbm_budget_bytes=64 << 30, max_batch_hits=cap, max_batch_events=8)
+        return sch.run(arrivals, n_hits).summary()
+
+    s = served(args.serve_rate)
     res["serving"] = {"workload": "Poisson stream of 100-layer x U[1000,10000]-hit events, device-resident pool",
                       "offered_events_per_s": args.serve_rate, "slots": 2, "hbm_budget_bytes": 64 << 30,
                       **{k: (round(v, 4) if isinstance(v, float) else v) for k, v in s.items()}}
+    if not args.no_sweep:
+        sweep = []
+        for rate in (100.0, 250.0, 500.0, 1000.0, 2000.0, 5000.0):
+            s = served(rate)
+            sweep.append({"offered_events_per_s": rate, "events": s["events"],
+                          "events_per_s": round(s["events_per_s"], 1), "hits_per_s": round(s["hits_per_s"], 1),
+                          "p50_ms": round(s["p50_ms"], 4), "p99_ms": round(s["p99_ms"], 4),
+                          "mean_batch_events": round(s["mean_batch_events"], 3)})
+            log(f"served {rate:g}/s: p50 {s['p50_ms']:.3f} ms p99 {s['p99_ms']:.3f} ms")
+        res["serving_sweep"] = sweep
     be.close()
     return res
 

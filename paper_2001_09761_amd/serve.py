@@ -228,7 +228,8 @@ class GpuPoolBackend:
         if next_arrival is not None and not busy:
             dt = next_arrival - self.now()
             if dt > 2e-4:
-                time.sleep(dt - 1e-4)
+                # short sleeps: a long one can overshoot by milliseconds
+                time.sleep(min(dt - 1e-4, 1e-3))
                 return
         time.sleep(2e-5)
 
