@@ -254,6 +254,7 @@ def main():
 
     if not args.no_extras:
         out.update(extras(args, params, log))
+        out["paper_workload"] = paper_workload(log)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(events, params)
     print(json.dumps(out), flush=True)
@@ -307,6 +308,80 @@ def traffic_summary(d, stage, n_events):
     with open(PROFILE_TRAFFIC, "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps(out))
+
+
+def paper_workload(log, batched_events=32):
+    """The paper's own performance study (Sec. 4.2, Table 2, Fig. 5): unit
+    weights, sigma = 3 cm clusters, dc = 3, rho_c = 8, delta_c = delta_o = 5,
+    5 cm bin; 100 layers of 1k..10k hits, one event per call, then a batch of
+    distinct 1M-hit events."""
+    import numpy as np
+    import torch
+
+    import paper_2001_09761_amd as clue
+    from paper_2001_09761_amd import gen
+
+    dev = torch.device("cuda", 0)
+    p = dict(gen.PAPER_PARAMS, extent=200.0, n_layers=100)
+    stream = torch.cuda.current_stream()
+    out = {"workload": "paper dataset: 100 layers, unit weights, sigma 3 cm clusters of 50, 5% noise, 200x200 cm",
+           "params": dict(gen.PAPER_PARAMS, bin_cm=gen.PAPER_BIN)}
+    sweep = []
+    with clue.Context(p["dc"], p["rho_c"], p["delta_c"], p["delta_o"], max_hits=1_000_000, extent=200.0,
+                      n_layers=100, tile_size=gen.PAPER_BIN) as ctx:
+        for k in range(1, 11):
+            ev = gen.paper_event(1000 * k, event_index=k)[0]
+            t = {n: torch.from_numpy(v).to(dev) for n, v in ev.items() if isinstance(v, np.ndarray)}
+            cid = torch.empty(ev["x"].size, dtype=torch.int32, device=dev)
+            seed = torch.empty(ev["x"].size, dtype=torch.uint8, device=dev)
+            run = lambda: ctx.run(t["x"], t["y"], t["layer"], t["energy"], cid, seed)  # noqa: E731
+            for _ in range(3):
+                run()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(10):
+                run()
+            e1.record(stream)
+            e1.synchronize()
+            ms = e0.elapsed_time(e1) / 10
+            sweep.append({"hits": int(ev["x"].size), "ms_per_event": round(ms, 4),
+                          "hits_per_s": round(ev["x"].size / ms * 1e3, 1)})
+        ctx.enable_stage_timing(True)
+        acc = {}
+        for _ in range(5):
+            run()
+            for n, v in ctx.stage_times().items():
+                acc[n] = acc.get(n, 0.0) + v / 5
+        ctx.enable_stage_timing(False)
+        ctx.status()
+    out["plain_sweep_bin5cm"] = sweep
+    out["stages_ms_1M_bin5cm"] = {n: round(v, 4) for n, v in acc.items()}
+    log(f"paper workload: 1M-hit event {sweep[-1]['ms_per_event']} ms at the 5 cm bin")
+
+    evs = [gen.paper_event(10000, event_index=100 + e)[0] for e in range(batched_events)]
+    b = gen.concat_events(evs)
+    d = {n: torch.from_numpy(v).to(dev) for n, v in b.items() if isinstance(v, np.ndarray)}
+    n = int(b["x"].size)
+    with clue.Context(p["dc"], p["rho_c"], p["delta_c"], p["delta_o"], max_hits=n, max_events=batched_events,
+                      extent=200.0, n_layers=100) as ctx:
+        tuning, src = apply_tuning(ctx, d, batched_events, p, log)
+        cid = torch.empty(n, dtype=torch.int32, device=dev)
+        seed = torch.empty(n, dtype=torch.uint8, device=dev)
+        run = lambda: ctx.run_batch(d["event"], batched_events, d["x"], d["y"], d["layer"], d["energy"], cid,  # noqa: E731
+                                    seed)
+        for _ in range(3):
+            run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(10):
+            run()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / 10
+        ctx.status()
+    out["batched"] = {"events": batched_events, "hits": n, "ms_per_step": round(dt * 1e3, 4),
+                      "hits_per_s": round(n / dt, 1), "tuning": tuning, "tuning_source": src}
+    return out
 
 
 def extras(args, params, log):

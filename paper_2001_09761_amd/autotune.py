@@ -218,17 +218,20 @@ def _main():
     from paper_2001_09761_amd import gen
 
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", choices=["cfg2", "cfg4"], default="cfg2")
+    ap.add_argument("--workload", choices=["cfg2", "cfg4", "paper"], default="cfg2")
     ap.add_argument("--events", type=int, default=32)
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--out", default=DEFAULT_CACHE)
     args = ap.parse_args()
     dev = torch.device("cuda", 0)
+    params = dict(gen.DEFAULT_PARAMS, extent=200.0, n_layers=100)
     if args.workload == "cfg2":
         evs = [gen.config2(seed=1, event_index=e)[0] for e in range(args.events)]
-    else:
+    elif args.workload == "cfg4":
         evs = [gen.config4_event(e) for e in range(args.events)]
-    params = dict(gen.DEFAULT_PARAMS, extent=200.0, n_layers=100)
+    else:
+        evs = [gen.paper_event(10000, event_index=e)[0] for e in range(args.events)]
+        params = dict(gen.PAPER_PARAMS, extent=200.0, n_layers=100)
     b = gen.concat_events(evs)
     batch = {k: torch.from_numpy(v).to(dev) for k, v in b.items() if isinstance(v, np.ndarray)}
     ctx = clue.Context(params["dc"], params["rho_c"], params["delta_c"], params["delta_o"], max_hits=b["x"].size,

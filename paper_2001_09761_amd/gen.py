@@ -17,6 +17,9 @@ the five benchmark configurations:
   (20 % noise, rings and crescents).
 * ``config4``: 64 events x 100 layers with U{1000..10000} hits per layer.
 * Poisson arrival times for the served form.
+* ``paper_event``: the paper's own performance dataset (unit weights,
+  sigma = 3 cm clusters, 5 % noise) for its parameters dc = 3, rho_c = 8,
+  delta_c = delta_o = 5 and a 5 cm bin.
 
 Every array is generated in float64 and cast to float32 (positions, energies)
 or int32 (layer and event ids). Each (event, layer) draws from its own
@@ -32,6 +35,10 @@ import numpy as np
 
 # Clustering parameters shared by the benchmark configurations (cm, energy).
 DEFAULT_PARAMS = dict(dc=2.0, rho_c=5.0, delta_c=2.0, delta_o=4.0)
+# Parameters of the paper's own performance study (Sec. 4.2): dc = 3 cm,
+# delta_o = delta_c = 5 cm, rho_c = 8, with a 5 cm bin.
+PAPER_PARAMS = dict(dc=3.0, rho_c=8.0, delta_c=5.0, delta_o=5.0)
+PAPER_BIN = 5.0
 
 
 @dataclass(frozen=True)
@@ -42,6 +49,7 @@ class LayerSpec:
     cluster_size: int = 20
     sigma: float = 1.0
     shape: str = "gauss"  # "gauss" or "hard" (rings and crescents)
+    unit_weight: bool = False  # every hit E = 1 (cluster shape carried by the density alone)
 
 
 def _split_even(total: int, parts: int) -> np.ndarray:
@@ -68,6 +76,8 @@ def gen_layer(rng: np.random.Generator, spec: LayerSpec):
             off = rng.normal(0.0, spec.sigma, size=(n_cl_hits, 2))
             r2 = (off * off).sum(axis=1)
             e = 10.0 * np.exp(-r2 / (2.0 * spec.sigma * spec.sigma))
+            if spec.unit_weight:
+                e = np.ones(n_cl_hits)
             pos = centres[owner] + off
         elif spec.shape == "hard":
             # Half rings, half crescents: radius U[3,8] cm, radial jitter
@@ -91,7 +101,8 @@ def gen_layer(rng: np.random.Generator, spec: LayerSpec):
         noise = rng.uniform(0.0, spec.extent, size=(n_noise, 2))
         xs.append(noise[:, 0])
         ys.append(noise[:, 1])
-        es.append(rng.uniform(0.0, 1.0, size=n_noise))
+        en = rng.uniform(0.0, 1.0, size=n_noise)
+        es.append(np.ones(n_noise) if spec.unit_weight else en)
     if not xs:
         z = np.zeros(0)
         return z, z, z
@@ -188,6 +199,18 @@ def config4(n_events: int = 64, seed: int = 5, n_layers: int = 100):
     """64 events x 100 layers x U{1000..10000} hits (about 35M hits)."""
     evs = [config4_event(e, seed=seed, n_layers=n_layers) for e in range(n_events)]
     return concat_events(evs), dict(DEFAULT_PARAMS, extent=200.0, n_layers=n_layers)
+
+
+def paper_event(hits_per_layer: int, seed: int = 7, event_index: int = 0, n_layers: int = 100,
+                cluster_size: int = 50, extent: float = 200.0):
+    """The paper's performance dataset (Sec. 4.2): 100 layers of unit-weight
+    hits, circular Gaussian clusters with sigma = 3 cm, 5 % uniform noise.
+    The paper fixes neither the layer extent nor the cluster size; these are
+    200 x 200 cm and 50 hits."""
+    spec = LayerSpec(n_hits=hits_per_layer, extent=extent, noise_frac=0.05, cluster_size=cluster_size, sigma=3.0,
+                     unit_weight=True)
+    ev = make_event([spec] * n_layers, seed=seed, event_index=event_index)
+    return ev, dict(PAPER_PARAMS, extent=extent, n_layers=n_layers)
 
 
 def poisson_arrivals(rate_hz: float, n: int, seed: int = 6) -> np.ndarray:

@@ -221,3 +221,23 @@ def test_capacity_and_argument_errors():
         assert ei.value.code == -1
     with pytest.raises(clue.ClueError):
         clue.Context(0.0, 5.0, 2.0, 4.0, max_hits=10, n_layers=1)
+
+
+@pytest.mark.parametrize("hpl", [1000, 10000])
+@pytest.mark.parametrize("tile", [0.0, 5.0])
+def test_paper_workload(hpl, tile):
+    """The paper's own study (Sec. 4.2): unit weights, sigma = 3 cm clusters,
+    dc = 3, rho_c = 8, delta_c = delta_o = 5; at its 5 cm bin (windows span up
+    to three tiles) and at the default tile."""
+    ev, p = gen.paper_event(hpl)
+    tuning = dict(tile_size=tile) if tile else None
+    assert_parity(gpu_run(ev, p, tuning=tuning), _ref(ev, p), where=f"paper {hpl}/layer tile {tile}")
+
+
+def test_paper_sweep_batched():
+    """The paper's linear-scaling sweep (1k..10k hits per layer) as one batch."""
+    evs = [gen.paper_event(1000 * s, event_index=s)[0] for s in range(1, 11)]
+    batch = gen.concat_events(evs)
+    p = dict(gen.PAPER_PARAMS, extent=200.0, n_layers=100)
+    got = gpu_run(batch, p, batched=True, n_events=10, tuning=dict(tile_size=gen.PAPER_BIN))
+    assert_parity(got, _ref(batch, p), where="paper sweep batched")
