@@ -20,6 +20,7 @@ backend and a virtual clock.
 """
 from __future__ import annotations
 
+import gc
 import time
 from dataclasses import dataclass, field
 
@@ -85,7 +86,18 @@ class Scheduler:
 
     def run(self, arrivals, n_hits):
         """Serves events 0..N-1 (pool order) arriving at ``arrivals`` seconds
-        after the start. Returns RunStats."""
+        after the start. Returns RunStats. The cyclic garbage collector is
+        paused for the duration (a full collection can stall the loop for
+        milliseconds)."""
+        enabled = gc.isenabled()
+        gc.disable()
+        try:
+            return self._run(arrivals, n_hits)
+        finally:
+            if enabled:
+                gc.enable()
+
+    def _run(self, arrivals, n_hits):
         be = self.backend
         N = len(arrivals)
         for i in range(N):
