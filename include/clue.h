@@ -137,6 +137,26 @@ int clue_run_batch_range(clue_ctx *c, int64_t n, int32_t first_event, int32_t n_
                          const float *energy, int32_t *cluster_id, uint8_t *is_seed, void *stream);
 
 /*
+ * Host-resident batched form: the same clustering as clue_run_batch, with
+ * every data pointer in HOST memory (the paper's timings include the copies,
+ * Sec. 4.2). The events are streamed through the context in chunks of whole
+ * events that fit its capacity (max_hits, max_events), so n may exceed
+ * max_hits: while chunk k is clustered, chunk k + 1 is copied in and chunk
+ * k - 1's results are copied out, on the context's own streams. Pinned host
+ * memory (hipHostMalloc) lets the copies overlap the kernels; pageable memory
+ * gives the same results with the copies serialised. `event` may be NULL when
+ * n_events == 1. Synchronous: returns once cluster_id and is_seed hold every
+ * result. The device staging (25 bytes per hit of capacity, two chunks) is
+ * allocated on the first call and counted against the HBM budget. Errors: an
+ * event larger than max_hits -> CLUE_ERR_CAPACITY; a device-side error of any
+ * chunk is returned as clue_status would. Intermediates and follower lists
+ * afterwards describe the last chunk.
+ */
+int clue_run_batch_host(clue_ctx *c, int64_t n, int32_t n_events, const int32_t *event, const float *x,
+                        const float *y, const int32_t *layer, const float *energy, int32_t *cluster_id,
+                        uint8_t *is_seed);
+
+/*
  * Copy the last run's per-hit intermediates into caller DEVICE buffers, in the
  * caller's hit order: rho float32[n] (Eq. 3), nh int32[n] (event-local, -1 if
  * none), delta2 float32[n] (squared separation, +inf if none). Any pointer may

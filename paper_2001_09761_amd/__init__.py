@@ -10,6 +10,8 @@ from __future__ import annotations
 
 import ctypes
 
+import numpy as np
+
 from . import _lib
 from ._lib import (ClueError, KEEP_INTERMEDIATES, NO_FOLLOWERS, TIE_PAPER_STRICT, VALIDATE,  # noqa: F401
                    make_params)
@@ -116,6 +118,37 @@ class Context:
                                            self._dev(cluster_id, torch.int32, "cluster_id", n),
                                            self._dev(is_seed, torch.uint8, "is_seed", n), self._stream(stream)))
         self._last_n = n
+        return cluster_id, is_seed
+
+    @staticmethod
+    def _host(t, np_dtype, name, n):
+        """Pointer to a contiguous host array (numpy array or CPU tensor)."""
+        torch = _torch()
+        if isinstance(t, torch.Tensor):
+            if t.device.type != "cpu":
+                raise TypeError(f"{name} must be in host memory")
+            t = t.numpy()
+        if not isinstance(t, np.ndarray) or t.dtype != np_dtype or not t.flags.c_contiguous or t.size < n:
+            raise TypeError(f"{name} must be a contiguous {np.dtype(np_dtype).name} host array of >= {n} elements")
+        return ctypes.c_void_p(t.ctypes.data if n > 0 else 0)
+
+    def run_batch_host(self, event, n_events, x, y, layer, energy, cluster_id=None, is_seed=None):
+        """Batched form over HOST arrays (numpy arrays or CPU tensors; pinned
+        tensors let copies overlap the kernels). The batch may exceed the
+        context capacity: it is streamed through in chunks of whole events.
+        Synchronous. Returns (cluster_id, is_seed) as host arrays."""
+        n = int(np.asarray(x).size) if not hasattr(x, "numel") else int(x.numel())
+        if cluster_id is None:
+            cluster_id = np.empty(n, dtype=np.int32)
+        if is_seed is None:
+            is_seed = np.empty(n, dtype=np.uint8)
+        ev = ctypes.c_void_p(0) if event is None else self._host(event, np.int32, "event", n)
+        self._check(self._L.clue_run_batch_host(self._ctx, n, int(n_events), ev, self._host(x, np.float32, "x", n),
+                                                self._host(y, np.float32, "y", n),
+                                                self._host(layer, np.int32, "layer", n),
+                                                self._host(energy, np.float32, "energy", n),
+                                                self._host(cluster_id, np.int32, "cluster_id", n),
+                                                self._host(is_seed, np.uint8, "is_seed", n)))
         return cluster_id, is_seed
 
     def run_batch_range(self, first_event, n_events, event, x, y, layer, energy, cluster_id, is_seed,

@@ -76,6 +76,7 @@ def load(path: str = LIB_PATH):
         "clue_run": ([P, i64, P, P, P, P, P, P, P], ctypes.c_int),
         "clue_run_batch": ([P, i64, i32, P, P, P, P, P, P, P, P], ctypes.c_int),
         "clue_run_batch_range": ([P, i64, i32, i32, P, P, P, P, P, P, P, P], ctypes.c_int),
+        "clue_run_batch_host": ([P, i64, i32, P, P, P, P, P, P, P], ctypes.c_int),
         "clue_get_intermediates": ([P, P, P, P, P], ctypes.c_int),
         "clue_get_followers": ([P, P, P, ctypes.POINTER(i64), P], ctypes.c_int),
         "clue_status": ([P, P], ctypes.c_int),

@@ -6,6 +6,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "clue.h"
 #include "clue_internal.h"
@@ -34,6 +35,11 @@ struct clue_ctx {
   hipEvent_t ev[S_COUNT + 1] = {};
   int64_t last_n = -1;
   int32_t last_events = 0;
+  // host-resident form: two device staging chunks and their streams/events
+  void* stage_base = nullptr;
+  int64_t stage_hits = 0;
+  hipStream_t h2d = nullptr, comp = nullptr, d2h = nullptr;
+  hipEvent_t in_ready[2] = {}, done[2] = {}, out_done[2] = {};
   bool last_followers_valid = false;
   std::string err;
 };
@@ -496,6 +502,138 @@ int clue_run_batch_range(clue_ctx* c, int64_t n, int32_t first_event, int32_t n_
   return run_common(c, n, n_events, first_event, event, x, y, layer, energy, cluster_id, is_seed, stream, true);
 }
 
+// Device staging of the host-resident form: per chunk x, y, E, layer, event
+// (4 bytes each) and cluster_id (4) + is_seed (1) for stage_hits hits.
+struct StageChunk {
+  float *x, *y, *e;
+  int32_t *layer, *event, *cid;
+  uint8_t* seed;
+};
+
+static StageChunk stage_chunk(clue_ctx* c, int k) {
+  const size_t n = (size_t)c->stage_hits;
+  auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t per = al(4 * n) * 6 + al(n);
+  char* b = (char*)c->stage_base + (size_t)k * per;
+  StageChunk s;
+  s.x = (float*)b;
+  s.y = (float*)(b + al(4 * n));
+  s.e = (float*)(b + 2 * al(4 * n));
+  s.layer = (int32_t*)(b + 3 * al(4 * n));
+  s.event = (int32_t*)(b + 4 * al(4 * n));
+  s.cid = (int32_t*)(b + 5 * al(4 * n));
+  s.seed = (uint8_t*)(b + 6 * al(4 * n));
+  return s;
+}
+
+static int ensure_staging(clue_ctx* c) {
+  if (c->stage_base && c->stage_hits == c->a.cap_hits) return CLUE_OK;
+  HIP_TRY(c, hipSetDevice(c->device));
+  if (c->stage_base) {
+    HIP_TRY(c, hipDeviceSynchronize());
+    hipFree(c->stage_base);
+    c->stage_base = nullptr;
+  }
+  const size_t n = (size_t)c->a.cap_hits;
+  auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t bytes = 2 * (al(4 * n) * 6 + al(n));
+  if (c->budget && c->arena_bytes + bytes > c->budget)
+    return set_err(c, CLUE_ERR_BUDGET, "host-form staging of " + std::to_string(bytes) + " bytes exceeds the HBM budget");
+  hipError_t e = hipMalloc(&c->stage_base, bytes);
+  if (e != hipSuccess) {
+    c->stage_base = nullptr;
+    return set_err(c, CLUE_ERR_NOMEM, "hipMalloc of the host-form staging failed");
+  }
+  c->stage_hits = (int64_t)n;
+  for (hipStream_t* st : {&c->h2d, &c->comp, &c->d2h})
+    if (!*st) HIP_TRY(c, hipStreamCreateWithFlags(st, hipStreamNonBlocking));
+  for (int i = 0; i < 2; ++i)
+    for (hipEvent_t* ev : {&c->in_ready[i], &c->done[i], &c->out_done[i]})
+      if (!*ev) HIP_TRY(c, hipEventCreateWithFlags(ev, hipEventDisableTiming));
+  return CLUE_OK;
+}
+
+int clue_run_batch_host(clue_ctx* c, int64_t n, int32_t n_events, const int32_t* event, const float* x,
+                        const float* y, const int32_t* layer, const float* energy, int32_t* cluster_id,
+                        uint8_t* is_seed) {
+  if (!c) return CLUE_ERR_ARG;
+  if (n < 0 || n >= ((int64_t)1 << 31) - 1) return set_err(c, CLUE_ERR_ARG, "n out of range");
+  if (n_events < 1) return set_err(c, CLUE_ERR_ARG, "n_events must be >= 1");
+  if (n > 0 && (!x || !y || !layer || !energy || !cluster_id || !is_seed))
+    return set_err(c, CLUE_ERR_ARG, "null input or output pointer");
+  if (n > 0 && n_events > 1 && !event) return set_err(c, CLUE_ERR_ARG, "null event ids");
+  c->timed_valid = false;
+  if (n == 0) {
+    c->last_n = 0;
+    c->last_events = n_events;
+    return CLUE_OK;
+  }
+  // first hit of every event (ids non-decreasing; clamped so that the
+  // chunks always tile [0, n))
+  std::vector<int64_t> start((size_t)n_events + 1, 0);
+  for (int32_t e = 0; e <= n_events; ++e) {
+    int64_t lo = 0, hi = n;
+    if (e == n_events || !event) {
+      lo = e == 0 ? 0 : n;
+    } else {
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) / 2;
+        if (event[mid] < e)
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+    }
+    start[e] = e == 0 ? 0 : std::max(lo, start[e - 1]);
+  }
+  start[n_events] = n;
+  // chunks of whole events within the capacity
+  std::vector<std::pair<int32_t, int32_t>> chunks;  // (first event, count)
+  for (int32_t e0 = 0; e0 < n_events;) {
+    int32_t e1 = e0;
+    while (e1 < n_events && e1 - e0 < c->a.cap_events && start[e1 + 1] - start[e0] <= c->a.cap_hits) ++e1;
+    if (e1 == e0)
+      return set_err(c, CLUE_ERR_CAPACITY, "event " + std::to_string(e0) + " has " +
+                                               std::to_string(start[e0 + 1] - start[e0]) +
+                                               " hits, more than the context capacity");
+    chunks.emplace_back(e0, e1 - e0);
+    e0 = e1;
+  }
+  int rc = ensure_staging(c);
+  if (rc != CLUE_OK) return rc;
+  for (size_t k = 0; k < chunks.size(); ++k) {
+    const int slot = (int)(k & 1);
+    const StageChunk sc = stage_chunk(c, slot);
+    const int32_t e0 = chunks[k].first, ne = chunks[k].second;
+    const int64_t h0 = start[e0], nh = start[e0 + ne] - h0;
+    if (k >= 2) HIP_TRY(c, hipStreamWaitEvent(c->h2d, c->done[slot], 0));  // inputs of chunk k - 2 consumed
+    HIP_TRY(c, hipMemcpyAsync(sc.x, x + h0, nh * 4, hipMemcpyHostToDevice, c->h2d));
+    HIP_TRY(c, hipMemcpyAsync(sc.y, y + h0, nh * 4, hipMemcpyHostToDevice, c->h2d));
+    HIP_TRY(c, hipMemcpyAsync(sc.e, energy + h0, nh * 4, hipMemcpyHostToDevice, c->h2d));
+    HIP_TRY(c, hipMemcpyAsync(sc.layer, layer + h0, nh * 4, hipMemcpyHostToDevice, c->h2d));
+    if (event) HIP_TRY(c, hipMemcpyAsync(sc.event, event + h0, nh * 4, hipMemcpyHostToDevice, c->h2d));
+    HIP_TRY(c, hipEventRecord(c->in_ready[slot], c->h2d));
+    HIP_TRY(c, hipStreamWaitEvent(c->comp, c->in_ready[slot], 0));
+    if (k >= 2) HIP_TRY(c, hipStreamWaitEvent(c->comp, c->out_done[slot], 0));  // outputs of chunk k - 2 copied
+    if (event)
+      rc = run_common(c, nh, ne, e0, sc.event, sc.x, sc.y, sc.layer, sc.e, sc.cid, sc.seed, c->comp, true);
+    else
+      rc = run_common(c, nh, 1, 0, nullptr, sc.x, sc.y, sc.layer, sc.e, sc.cid, sc.seed, c->comp, true);
+    if (rc != CLUE_OK) {
+      hipDeviceSynchronize();
+      return rc;
+    }
+    HIP_TRY(c, hipEventRecord(c->done[slot], c->comp));
+    HIP_TRY(c, hipStreamWaitEvent(c->d2h, c->done[slot], 0));
+    HIP_TRY(c, hipMemcpyAsync(cluster_id + h0, sc.cid, nh * 4, hipMemcpyDeviceToHost, c->d2h));
+    HIP_TRY(c, hipMemcpyAsync(is_seed + h0, sc.seed, nh, hipMemcpyDeviceToHost, c->d2h));
+    HIP_TRY(c, hipEventRecord(c->out_done[slot], c->d2h));
+  }
+  HIP_TRY(c, hipStreamSynchronize(c->d2h));
+  HIP_TRY(c, hipStreamSynchronize(c->comp));
+  return clue_status(c, c->comp);
+}
+
 int clue_get_intermediates(clue_ctx* c, float* rho, int32_t* nh, float* delta2, void* stream) {
   if (!c) return CLUE_ERR_ARG;
   if (!(c->params.flags & CLUE_KEEP_INTERMEDIATES))
@@ -635,6 +773,12 @@ void clue_destroy(clue_ctx* c) {
   hipDeviceSynchronize();
   drop_graph(c);
   if (c->cap_stream) hipStreamDestroy(c->cap_stream);
+  for (hipStream_t st : {c->h2d, c->comp, c->d2h})
+    if (st) hipStreamDestroy(st);
+  for (int i = 0; i < 2; ++i)
+    for (hipEvent_t e : {c->in_ready[i], c->done[i], c->out_done[i]})
+      if (e) hipEventDestroy(e);
+  if (c->stage_base) hipFree(c->stage_base);
   for (int i = 0; i <= S_COUNT; ++i)
     if (c->ev[i]) hipEventDestroy(c->ev[i]);
   if (c->arena_base) hipFree(c->arena_base);
