@@ -253,6 +253,7 @@ def main():
     }
 
     if not args.no_extras:
+        out["host_resident"] = host_resident(events, params, log)
         out.update(extras(args, params, log))
         out["paper_workload"] = paper_workload(log)
     if not args.no_cpu:
@@ -381,6 +382,53 @@ def paper_workload(log, batched_events=32):
         ctx.status()
     out["batched"] = {"events": batched_events, "hits": n, "ms_per_step": round(dt * 1e3, 4),
                       "hits_per_s": round(n / dt, 1), "tuning": tuning, "tuning_source": src}
+    return out
+
+
+def host_resident(events, params, log):
+    """PCIe-inclusive rate: the same 32-event batch in pinned host memory,
+    clustered by clue_run_batch_host with the whole batch as one chunk, and
+    streamed through a context a quarter of its size (copies overlapping
+    kernels)."""
+    import numpy as np
+    import torch
+
+    import paper_2001_09761_amd as clue
+    from paper_2001_09761_amd import gen
+
+    b = gen.concat_events(events)
+    n, ne = int(b["x"].size), len(events)
+    h = {k: torch.from_numpy(b[k]).pin_memory() for k in ("event", "x", "y", "layer", "energy")}
+    cid = torch.empty(n, dtype=torch.int32).pin_memory()
+    seed = torch.empty(n, dtype=torch.uint8).pin_memory()
+    out = {"hits": n, "events": ne, "host_memory": "pinned"}
+    for label, cap_events in (("one_chunk", ne), ("chunks_of_8_events", 8)):
+        cap_hits = n if cap_events == ne else 8 * max(e["x"].size for e in events)
+        with clue.Context(params["dc"], params["rho_c"], params["delta_c"], params["delta_o"], max_hits=cap_hits,
+                          max_events=cap_events, extent=200.0, n_layers=100) as ctx:
+            d = {k: v[:cap_hits].cuda() for k, v in h.items()}
+            apply_tuning(ctx, d, cap_events, params, log)
+            del d
+            run = lambda: ctx.run_batch_host(h["event"], ne, h["x"], h["y"], h["layer"], h["energy"], cid, seed)  # noqa: E731
+            run()
+            t0 = time.perf_counter()
+            for _ in range(5):
+                run()
+            dt = (time.perf_counter() - t0) / 5
+        out[label] = {"ms_per_batch": round(dt * 1e3, 3), "hits_per_s": round(n / dt, 1)}
+    # plain pinned copies of the same bytes, for reference
+    dev = torch.device("cuda", 0)
+    ins = [v.to(dev, non_blocking=True) for v in h.values()]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        ins = [v.to(dev, non_blocking=True) for v in h.values()]
+    torch.cuda.synchronize()
+    t_in = (time.perf_counter() - t0) / 5
+    nbytes = sum(v.numel() * v.element_size() for v in h.values())
+    out["h2d_GBps_inputs"] = round(nbytes / t_in / 1e9, 1)
+    log(f"host-resident: one chunk {out['one_chunk']['ms_per_batch']} ms, chunked "
+        f"{out['chunks_of_8_events']['ms_per_batch']} ms")
     return out
 
 
