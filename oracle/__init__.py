@@ -25,7 +25,10 @@ class OracleParams(ctypes.Structure):
         ("x_max", ctypes.c_float), ("y_max", ctypes.c_float),
         ("n_layers", ctypes.c_int32), ("bin_size", ctypes.c_float),
         ("paper_strict", ctypes.c_int32), ("brute_force", ctypes.c_int32),
+        ("kernel", ctypes.c_int32), ("kernel_scale", ctypes.c_float),
     ]
+
+KERNELS = {"flat": 0, "gaussian": 1, "exponential": 2}
 
 
 class OracleError(RuntimeError):
@@ -46,6 +49,8 @@ def lib():
                                  P, P, P, P, P, P, P, P, P, P, P, P, P, ctypes.c_int]
         L.oracle_run.restype = ctypes.c_int
         L.oracle_last_error.restype = ctypes.c_char_p
+        L.oracle_exp32.argtypes = [P, P, ctypes.c_int64]
+        L.oracle_exp32.restype = None
         _lib = L
     return _lib
 
@@ -56,7 +61,8 @@ def _ptr(a):
 
 def run(x, y, layer, energy, *, dc, rho_c, delta_c, delta_o, extent=None, bounds=None,
         n_layers=None, event=None, n_events=None, bin_size=0.0, paper_strict=False,
-        brute_force=False, n_threads=1, want=("rho", "rho64", "nh", "delta2", "followers")):
+        brute_force=False, kernel="flat", kernel_scale=0.0, n_threads=1,
+        want=("rho", "rho64", "nh", "delta2", "followers")):
     """Run the oracle on host arrays. Returns a dict of numpy arrays.
 
     ``bounds=(x_min, y_min, x_max, y_max)`` or ``extent=s`` for [0, s]^2."""
@@ -78,7 +84,8 @@ def run(x, y, layer, energy, *, dc, rho_c, delta_c, delta_o, extent=None, bounds
     if n_events is None:
         n_events = 1
     p = OracleParams(dc, rho_c, delta_c, delta_o, bounds[0], bounds[1], bounds[2], bounds[3],
-                     int(n_layers), float(bin_size), int(bool(paper_strict)), int(bool(brute_force)))
+                     int(n_layers), float(bin_size), int(bool(paper_strict)), int(bool(brute_force)),
+                     KERNELS[kernel], float(kernel_scale))
     out = dict(cluster_id=np.empty(n, np.int32), is_seed=np.empty(n, np.uint8))
     if "rho" in want:
         out["rho"] = np.empty(n, np.float32)
@@ -104,6 +111,14 @@ def run(x, y, layer, energy, *, dc, rho_c, delta_c, delta_o, extent=None, bounds
     return out
 
 
+def exp32(x):
+    """The oracle's binary32 exponential (x <= 0) on an array."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    out = np.empty_like(x)
+    lib().oracle_exp32(_ptr(x), _ptr(out), x.size)
+    return out
+
+
 def run_event(ev, params, **kw):
     """Convenience wrapper: ``ev`` from the input generators, ``params`` dict
     with dc, rho_c, delta_c, delta_o, extent and n_layers."""
@@ -111,4 +126,5 @@ def run_event(ev, params, **kw):
                delta_c=params["delta_c"], delta_o=params["delta_o"],
                extent=params.get("extent"), bounds=params.get("bounds"),
                n_layers=params.get("n_layers"), event=ev.get("event"),
-               n_events=ev.get("n_events"), **kw)
+               n_events=ev.get("n_events"), kernel=params.get("kernel", "flat"),
+               kernel_scale=params.get("kernel_scale", 0.0), **kw)

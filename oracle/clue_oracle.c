@@ -33,6 +33,56 @@ static float dist2(float xi, float yi, float xj, float yj) {
   return dx2 + dy2;
 }
 
+/*
+ * exp(x) for x <= 0 in binary32 arithmetic, used by the Gaussian and
+ * exponential kernels of Eq. 3. Range reduction after Cody and Waite
+ * (Software Manual for the Elementary Functions, 1980): x = k ln2 + r with
+ * k = floor(x / ln2 + 1/2), ln2 split into a part with trailing zero bits
+ * (so k * hi is exact) and the remainder; exp(r) by its degree-7 Taylor
+ * polynomial in Horner form; the result scaled by 2^k. Every operation is
+ * one binary32 rounding, so the value is a fixed function of x. Results
+ * below 2^-125 (k < -125) are defined as 0.
+ */
+static float exp32(float x) {
+  const float inv_ln2 = (float)(1.0 / 0.69314718055994530942);
+  const float ln2_hi = 0.693145751953125f;
+  const float ln2_lo = (float)(0.69314718055994530942 - 0.693145751953125);
+  const float t = x * inv_ln2;
+  const float kf = floorf(t + 0.5f);
+  if (!(kf >= -125.0f)) return 0.0f;
+  const float r = (x - kf * ln2_hi) - kf * ln2_lo;
+  float p = (float)(1.0 / 5040.0);
+  p = p * r + (float)(1.0 / 720.0);
+  p = p * r + (float)(1.0 / 120.0);
+  p = p * r + (float)(1.0 / 24.0);
+  p = p * r + (float)(1.0 / 6.0);
+  p = p * r + 0.5f;
+  p = p * r + 1.0f;
+  p = p * r + 1.0f;
+  union { uint32_t u; float f; } two_k;
+  two_k.u = (uint32_t)((int32_t)kf + 127) << 23;
+  return p * two_k.f;
+}
+
+void oracle_exp32(const float *x, float *out, int64_t n) {
+  for (int64_t i = 0; i < n; ++i) out[i] = exp32(x[i]);
+}
+
+/* Kernel weight chi(d) of Eq. 3 for a pair at float32 squared distance d2:
+ * 1 (flat), exp(-d^2 / (2 s^2)) (Gaussian) or exp(-d / s) (exponential);
+ * a = fl(1 / (2 s^2)) or fl(1 / s); d = sqrtf(d2), correctly rounded. */
+static float kernel_weight(int kernel, float a, float d2) {
+  if (kernel == 1) return exp32(-(d2 * a));
+  if (kernel == 2) return exp32(-(sqrtf(d2) * a));
+  return 1.0f;
+}
+
+static double kernel_weight64(int kernel, double s, double d2) {
+  if (kernel == 1) return exp(-d2 / (2.0 * s * s));
+  if (kernel == 2) return exp(-sqrt(d2) / s);
+  return 1.0;
+}
+
 /* One (event, layer) unit with its own fixed grid (Sec. 2.1). */
 typedef struct {
   const float *x, *y, *e;  /* event-local base pointers */
@@ -52,6 +102,7 @@ typedef struct {
   double bin;
   float dc2, dm2;
   float dm;
+  float ka;  /* kernel constant: fl(1 / (2 s^2)) or fl(1 / s) */
 } ctx_t;
 
 /* Bin coordinate of a position: floor((v - lo) / bin) clamped to the grid. */
@@ -98,8 +149,8 @@ static int32_t gather_window(const ctx_t *c, const unit_t *u, int32_t i, float d
   return m;
 }
 
-/* Algorithm 1 / Eq. 3 with the flat kernel: rho_i = sum of w_j over N_dc(i),
- * added in ascending j. */
+/* Algorithm 1 / Eq. 3: rho_i = sum of fl(chi(d_ij) * w_j) over N_dc(i), added
+ * in ascending j (chi = 1 for the flat kernel: the weights themselves). */
 static void unit_density(const ctx_t *c, unit_t *u, int32_t *scratch) {
   for (int32_t a = 0; a < u->count; ++a) {
     int32_t i = u->ids[a];
@@ -109,9 +160,12 @@ static void unit_density(const ctx_t *c, unit_t *u, int32_t *scratch) {
     double acc64 = 0.0;
     for (int32_t k = 0; k < m; ++k) {
       int32_t j = scratch[k];
-      if (dist2(u->x[i], u->y[i], u->x[j], u->y[j]) < c->dc2) {
-        acc = acc + u->e[j];
-        acc64 = acc64 + (double)u->e[j];
+      const float d2 = dist2(u->x[i], u->y[i], u->x[j], u->y[j]);
+      if (d2 < c->dc2) {
+        const int kern = c->p->kernel;
+        const float w = kern ? kernel_weight(kern, c->ka, d2) * u->e[j] : u->e[j];
+        acc = acc + w;
+        acc64 = acc64 + kernel_weight64(kern, (double)c->p->kernel_scale, (double)d2) * (double)u->e[j];
       }
     }
     u->rho[i] = acc;
@@ -236,6 +290,9 @@ int oracle_run(const oracle_params *p, int64_t n, int32_t n_events, const int32_
       !(p->x_max > p->x_min) || !(p->y_max > p->y_min))
     return fail(ORACLE_ERR_ARG, "bad grid extent");
   if (p->n_layers < 1) return fail(ORACLE_ERR_ARG, "n_layers < 1");
+  if (p->kernel < 0 || p->kernel > 2) return fail(ORACLE_ERR_ARG, "unknown kernel");
+  if (p->kernel != 0 && !(p->kernel_scale > 0.0f && finite_f(p->kernel_scale)))
+    return fail(ORACLE_ERR_ARG, "kernel_scale must be positive");
   if (n == 0) {
     if (fstart) fstart[0] = 0;
     if (n_clusters)
@@ -261,6 +318,9 @@ int oracle_run(const oracle_params *p, int64_t n, int32_t n_events, const int32_
   c.dm = p->delta_o > p->delta_c ? p->delta_o : p->delta_c;
   c.dc2 = p->dc * p->dc;
   c.dm2 = c.dm * c.dm;
+  c.ka = 0.0f;
+  if (p->kernel == 1) c.ka = (float)(1.0 / (2.0 * (double)p->kernel_scale * (double)p->kernel_scale));
+  if (p->kernel == 2) c.ka = (float)(1.0 / (double)p->kernel_scale);
   {
     double b = p->bin_size > 0.0f ? (double)p->bin_size : (double)(p->dc > c.dm ? p->dc : c.dm);
     double dmax = (double)(p->dc > c.dm ? p->dc : c.dm);

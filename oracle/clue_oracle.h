@@ -8,7 +8,8 @@
  *
  * It follows the paper step by step:
  *   fixed-grid index      Sec. 2.1, Eq. 1 (Omega_d) and Eq. 2 (N_d)
- *   local density rho     Eq. 3, Algorithm 1 (flat kernel: chi = 1)
+ *   local density rho     Eq. 3, Algorithm 1 (kernel chi flat, Gaussian or
+ *                         exponential; see oracle_exp32)
  *   nearest-higher/delta  Eq. 4, Algorithm 2, d_m = max(delta_o, delta_c)
  *   seeds/outliers        Sec. 2.2 thresholds, first loop of Algorithm 3
  *   followers F_i         Eq. 5, first loop of Algorithm 3
@@ -56,6 +57,8 @@ typedef struct {
   float bin_size;                        /* oracle grid bin (cm); <= 0 -> max(dc, d_m) */
   int32_t paper_strict;                  /* 1: higher <=> rho_j > rho_i only */
   int32_t brute_force;                   /* 1: Omega = every hit of the same layer */
+  int32_t kernel;                        /* chi of Eq. 3: 0 flat, 1 Gaussian, 2 exponential */
+  float kernel_scale;                    /* s (cm): exp(-d^2 / (2 s^2)) or exp(-d / s) */
 } oracle_params;
 
 /*
@@ -77,6 +80,10 @@ int oracle_run(const oracle_params *p, int64_t n, int32_t n_events, const int32_
                int32_t *fstart, int32_t *flist, int32_t *n_clusters, int n_threads);
 
 const char *oracle_last_error(void);
+
+/* The binary32 exponential the Gaussian and exponential kernels use, for
+ * x <= 0 (definition in clue_oracle.c); out[i] = exp32(x[i]). */
+void oracle_exp32(const float *x, float *out, int64_t n);
 
 #ifdef __cplusplus
 }
