@@ -82,7 +82,16 @@ typedef struct {
   float tile_size;           /* grid tile side (cm); <= 0: default */
   int32_t threads_per_query; /* lanes per nearest-higher query (1, 2, 4); <= 0: default */
   uint32_t flags;            /* CLUE_* flags above */
+  int32_t kernel;            /* chi of Eq. 3 (Sec. 2.2): CLUE_KERNEL_FLAT (chi = 1),
+                                CLUE_KERNEL_GAUSSIAN exp(-d^2 / (2 s^2)) or
+                                CLUE_KERNEL_EXPONENTIAL exp(-d / s); rho_i sums
+                                fl(chi(d_ij) * energy_j) in ascending j. exp is one
+                                fixed binary32 evaluation (Cody-Waite reduction,
+                                degree-7 Taylor polynomial; 0 below 2^-125) */
+  float kernel_scale;        /* s (cm), > 0 for the Gaussian and exponential kernels */
 } clue_params;
+
+enum { CLUE_KERNEL_FLAT = 0, CLUE_KERNEL_GAUSSIAN = 1, CLUE_KERNEL_EXPONENTIAL = 2 };
 
 typedef struct clue_ctx clue_ctx;
 

@@ -33,8 +33,9 @@ def _bounds(extent=None, bounds=None):
 
 
 def footprint_bytes(dc, rho_c, delta_c, delta_o, max_hits, max_events=1, *, extent=None, bounds=None,
-                    n_layers=100, tile_size=0.0, flags=0) -> int:
-    p = make_params(dc, rho_c, delta_c, delta_o, _bounds(extent, bounds), n_layers, tile_size, 0, flags)
+                    n_layers=100, tile_size=0.0, flags=0, kernel="flat", kernel_scale=0.0) -> int:
+    p = make_params(dc, rho_c, delta_c, delta_o, _bounds(extent, bounds), n_layers, tile_size, 0, flags, kernel,
+                    kernel_scale)
     out = ctypes.c_uint64(0)
     _lib.check(_lib.load().clue_footprint_bytes(ctypes.byref(p), int(max_hits), int(max_events),
                                                 ctypes.byref(out)))
@@ -45,12 +46,13 @@ class Context:
     """One libclue context (scratch arena, captured graph) on one device."""
 
     def __init__(self, dc, rho_c, delta_c, delta_o, *, max_hits, max_events=1, extent=None, bounds=None,
-                 n_layers=100, tile_size=0.0, threads_per_query=0, flags=0, device=None, hbm_budget=0):
+                 n_layers=100, tile_size=0.0, threads_per_query=0, flags=0, device=None, hbm_budget=0,
+                 kernel="flat", kernel_scale=0.0):
         torch = _torch()
         self._L = _lib.load()
         self.device = torch.cuda.current_device() if device is None else int(device)
         self.params = make_params(dc, rho_c, delta_c, delta_o, _bounds(extent, bounds), n_layers, tile_size,
-                                  threads_per_query, flags)
+                                  threads_per_query, flags, kernel, kernel_scale)
         self.flags = int(flags)
         self._ctx = ctypes.c_void_p(None)
         rc = self._L.clue_create(ctypes.byref(self._ctx), ctypes.byref(self.params), self.device, int(max_hits),

@@ -28,7 +28,11 @@ class ClueParams(ctypes.Structure):
         ("x_max", ctypes.c_float), ("y_max", ctypes.c_float),
         ("n_layers", ctypes.c_int32), ("tile_size", ctypes.c_float),
         ("threads_per_query", ctypes.c_int32), ("flags", ctypes.c_uint32),
+        ("kernel", ctypes.c_int32), ("kernel_scale", ctypes.c_float),
     ]
+
+
+KERNELS = {"flat": 0, "gaussian": 1, "exponential": 2}
 
 
 class ClueTuning(ctypes.Structure):
@@ -95,10 +99,11 @@ def load(path: str = LIB_PATH):
     return L
 
 
-def make_params(dc, rho_c, delta_c, delta_o, bounds, n_layers, tile_size=0.0, threads_per_query=0, flags=0):
+def make_params(dc, rho_c, delta_c, delta_o, bounds, n_layers, tile_size=0.0, threads_per_query=0, flags=0,
+                kernel="flat", kernel_scale=0.0):
     return ClueParams(float(dc), float(rho_c), float(delta_c), float(delta_o), float(bounds[0]),
                       float(bounds[1]), float(bounds[2]), float(bounds[3]), int(n_layers), float(tile_size),
-                      int(threads_per_query), int(flags))
+                      int(threads_per_query), int(flags), KERNELS[kernel], float(kernel_scale))
 
 
 def check(rc: int, ctx=None):

@@ -85,6 +85,11 @@ static int plan_geom(const clue_params& p, float tile, int tpq, int bx, int by, 
     msg = "n_layers must be >= 1";
     return CLUE_ERR_ARG;
   }
+  if (p.kernel < CLUE_KERNEL_FLAT || p.kernel > CLUE_KERNEL_EXPONENTIAL ||
+      (p.kernel != CLUE_KERNEL_FLAT && !(finite(p.kernel_scale) && p.kernel_scale > 0.0f))) {
+    msg = "kernel must be flat, Gaussian or exponential, with kernel_scale > 0 for the latter two";
+    return CLUE_ERR_ARG;
+  }
   if (tpq != 1 && tpq != 2 && tpq != 4 && tpq != 8) {
     msg = "threads_per_query must be 1, 2, 4 or 8";
     return CLUE_ERR_ARG;
@@ -120,6 +125,10 @@ static int plan_geom(const clue_params& p, float tile, int tpq, int bx, int by, 
   g.tpl = g.nx * g.ny;
   g.L = p.n_layers;
   g.dc2 = p.dc * p.dc;
+  g.kernel = p.kernel;
+  g.ka = p.kernel == CLUE_KERNEL_GAUSSIAN
+             ? (float)(1.0 / (2.0 * (double)p.kernel_scale * (double)p.kernel_scale))
+             : (p.kernel == CLUE_KERNEL_EXPONENTIAL ? (float)(1.0 / (double)p.kernel_scale) : 0.0f);
   g.dm2 = dm * dm;
   g.dcs2 = p.delta_c * p.delta_c;
   g.do2 = p.delta_o * p.delta_o;

@@ -70,6 +70,8 @@ struct Geom {
   int32_t ts_ints;  // LDS ints for a region's tile offsets: rows * (cols + 1) + 1
   int32_t q_ints;   // LDS ints for the quad-list offsets: (bx + 1) * (by + 1) + 1
   float dc2;        // fl(dc*dc)
+  int32_t kernel;   // density kernel: 0 flat, 1 Gaussian, 2 exponential
+  float ka;         // its constant: fl(1 / (2 s^2)) or fl(1 / s)
   float dm2;        // fl(dm*dm), dm = max(delta_o, delta_c)
   float dcs2;       // fl(delta_c*delta_c)
   float do2;        // fl(delta_o*delta_o)

@@ -627,13 +627,73 @@ __device__ __forceinline__ Window query_window(const Geom& g, float w, float xi,
 // passing hits of the (at most MAXL x MAXL) sorted tile lists.
 // Records: (x, y, E, hit index as bits).
 // ---------------------------------------------------------------------------
-template <int MAXL>
+// exp(x) for x <= 0 as one fixed binary32 evaluation, after Cody and Waite's
+// range reduction: x = k ln2 + r with k = floor(x / ln2 + 1/2) and ln2 split
+// into a high part with trailing zero bits (k * hi exact) and the remainder;
+// exp(r) by its degree-7 Taylor polynomial in Horner form; then the scale by
+// 2^k. Every step is an explicit binary32 rounding, so any IEEE evaluation of
+// the same steps gives the same bits. 0 when k < -125.
+__device__ __forceinline__ float exp32(float x) {
+  constexpr float inv_ln2 = (float)(1.0 / 0.69314718055994530942);
+  constexpr float ln2_hi = 0.693145751953125f;
+  constexpr float ln2_lo = (float)(0.69314718055994530942 - 0.693145751953125);
+  const float kf = floorf(__fadd_rn(__fmul_rn(x, inv_ln2), 0.5f));
+  if (!(kf >= -125.0f)) return 0.0f;
+  const float r = __fsub_rn(__fsub_rn(x, __fmul_rn(kf, ln2_hi)), __fmul_rn(kf, ln2_lo));
+  float p = (float)(1.0 / 5040.0);
+  p = __fadd_rn(__fmul_rn(p, r), (float)(1.0 / 720.0));
+  p = __fadd_rn(__fmul_rn(p, r), (float)(1.0 / 120.0));
+  p = __fadd_rn(__fmul_rn(p, r), (float)(1.0 / 24.0));
+  p = __fadd_rn(__fmul_rn(p, r), (float)(1.0 / 6.0));
+  p = __fadd_rn(__fmul_rn(p, r), 0.5f);
+  p = __fadd_rn(__fmul_rn(p, r), 1.0f);
+  p = __fadd_rn(__fmul_rn(p, r), 1.0f);
+  return __fmul_rn(p, __uint_as_float((unsigned)((int)kf + 127) << 23));
+}
+
+// Correctly rounded binary32 square root of x >= 0: the hardware estimate
+// (within an ulp) is corrected by comparing x with the squares of the
+// midpoints to its neighbours, which are exact in binary64. Subnormal x is
+// scaled by 2^64 first (exact, and exactly undone by 2^-32).
+__device__ __forceinline__ float sqrt_rn(float x) {
+  if (!(x > 0.0f) || x == __int_as_float(0x7f800000)) return x;
+  const bool tiny = x < 1.17549435e-38f;
+  const float xs = tiny ? __fmul_rn(x, 18446744073709551616.0f) : x;
+  float s = __builtin_sqrtf(xs);
+  const double xd = (double)xs;
+  const float up = __uint_as_float(__float_as_uint(s) + 1u);
+  const double mh = 0.5 * ((double)s + (double)up);
+  if (mh * mh < xd) {
+    s = up;
+  } else {
+    const float dn = __uint_as_float(__float_as_uint(s) - 1u);
+    const double ml = 0.5 * ((double)dn + (double)s);
+    if (ml * ml > xd) s = dn;
+  }
+  return tiny ? __fmul_rn(s, 2.3283064365386963e-10f) : s;
+}
+
+// One term of Eq. 3 for a neighbour at squared distance d2 with energy e:
+// e (flat kernel), fl(exp(-fl(d2 a)) e) (Gaussian, a = 1 / (2 s^2)) or
+// fl(exp(-fl(sqrt(d2) a)) e) (exponential, a = 1 / s).
+template <int K>
+__device__ __forceinline__ float kernel_term(float d2, float ka, float e) {
+  if constexpr (K == 0) {
+    return e;
+  } else if constexpr (K == 1) {
+    return __fmul_rn(exp32(-__fmul_rn(d2, ka)), e);
+  } else {
+    return __fmul_rn(exp32(-__fmul_rn(sqrt_rn(d2), ka)), e);
+  }
+}
+
+template <int MAXL, int K>
 __device__ __forceinline__ float density_merge_full(const float4* __restrict__ rec, const int* lo, const int* hi, float xi, float yi,
-                                    float dc2) {
-  constexpr int K = MAXL * MAXL;
-  int cur[K], head[K];
+                                    float dc2, float ka) {
+  constexpr int NL = MAXL * MAXL;
+  int cur[NL], head[NL];
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
+  for (int k = 0; k < NL; ++k) {
     cur[k] = lo[k];
     head[k] = cur[k] < hi[k] ? __float_as_int(rec[cur[k]].w) : INT_MAX;
   }
@@ -641,23 +701,24 @@ __device__ __forceinline__ float density_merge_full(const float4* __restrict__ r
   for (;;) {
     int m = head[0];
 #pragma unroll
-    for (int k = 1; k < K; ++k) m = min(m, head[k]);
+    for (int k = 1; k < NL; ++k) m = min(m, head[k]);
     if (m == INT_MAX) break;
     int p = 0;
 #pragma unroll
-    for (int k = 0; k < K; ++k)
+    for (int k = 0; k < NL; ++k)
       if (head[k] == m) p = cur[k];
     const float4 r = rec[p];
-    if (dist2(xi, yi, r.x, r.y) < dc2) acc = __fadd_rn(acc, r.z);
+    const float d2 = dist2(xi, yi, r.x, r.y);
+    if (d2 < dc2) acc = __fadd_rn(acc, kernel_term<K>(d2, ka, r.z));
     const int np = p + 1;
     int nh = INT_MAX;
     bool more = false;
 #pragma unroll
-    for (int k = 0; k < K; ++k)
+    for (int k = 0; k < NL; ++k)
       if (head[k] == m) more = np < hi[k];
     if (more) nh = __float_as_int(rec[np].w);
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
+    for (int k = 0; k < NL; ++k) {
       if (head[k] == m) {
         cur[k] = np;
         head[k] = nh;
@@ -672,14 +733,14 @@ __device__ __forceinline__ int lowbit64(unsigned lo, unsigned hi) {
   return lo ? __builtin_ctz(lo) : 32 + __builtin_ctz(hi);
 }
 
-template <int MAXL>
+template <int MAXL, int K>
 __device__ __forceinline__ float density_two_pass(const float4* __restrict__ rec, const int* lo, const int* hi,
-                                                  float xi, float yi, float dc2) {
-  constexpr int K = MAXL * MAXL;
-  unsigned mlo[K], mhi[K];
+                                                  float xi, float yi, float dc2, float ka) {
+  constexpr int NL = MAXL * MAXL;
+  unsigned mlo[NL], mhi[NL];
   bool big = false;
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
+  for (int k = 0; k < NL; ++k) {
     mlo[k] = 0u;
     mhi[k] = 0u;
     const int len = hi[k] - lo[k];
@@ -707,31 +768,31 @@ __device__ __forceinline__ float density_two_pass(const float4* __restrict__ rec
       mhi[k] |= (dist2(xi, yi, q.x, q.y) < dc2 ? 1u : 0u) << (c - 32);
     }
   }
-  if (big) return density_merge_full<MAXL>(rec, lo, hi, xi, yi, dc2);
-  int hh[K];
-  float ee[K];
+  if (big) return density_merge_full<MAXL, K>(rec, lo, hi, xi, yi, dc2, ka);
+  int hh[NL];
+  float ee[NL];
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
+  for (int k = 0; k < NL; ++k) {
     hh[k] = INT_MAX;
     ee[k] = 0.0f;
     if (mlo[k] | mhi[k]) {
       const float4 r = rec[lo[k] + lowbit64(mlo[k], mhi[k])];
       hh[k] = __float_as_int(r.w);
-      ee[k] = r.z;
+      ee[k] = kernel_term<K>(dist2(xi, yi, r.x, r.y), ka, r.z);
     }
   }
   float acc = 0.0f;
   for (;;) {
     int m = hh[0];
 #pragma unroll
-    for (int k = 1; k < K; ++k) m = min(m, hh[k]);
+    for (int k = 1; k < NL; ++k) m = min(m, hh[k]);
     if (m == INT_MAX) break;
     // the selected list: take its head, drop its lowest passing bit
     float e = ee[0];
     unsigned ml = mlo[0], mh = mhi[0];
     int base = lo[0];
 #pragma unroll
-    for (int k = 1; k < K; ++k) {
+    for (int k = 1; k < NL; ++k) {
       if (hh[k] == m) {
         e = ee[k];
         ml = mlo[k];
@@ -747,13 +808,14 @@ __device__ __forceinline__ float density_two_pass(const float4* __restrict__ rec
     const bool more = (ml | mh) != 0u;
     float4 r = make_float4(0.0f, 0.0f, 0.0f, __int_as_float(INT_MAX));
     if (more) r = rec[base + lowbit64(ml, mh)];
+    const float en = more ? kernel_term<K>(dist2(xi, yi, r.x, r.y), ka, r.z) : 0.0f;
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
+    for (int k = 0; k < NL; ++k) {
       if (hh[k] == m) {
         mlo[k] = ml;
         mhi[k] = mh;
         hh[k] = __float_as_int(r.w);
-        ee[k] = r.z;
+        ee[k] = en;
       }
     }
   }
@@ -763,26 +825,29 @@ __device__ __forceinline__ float density_two_pass(const float4* __restrict__ rec
 // Global-memory density (tiles too dense to stage): the neighbours are
 // visited in ascending index by repeatedly taking the smallest index above
 // the previous one.
+template <int K>
 __device__ __forceinline__ float density_global(const Geom& g, const Arena& a, int64_t ubase, float xi, float yi) {
   const Window W = query_window(g, g.win_dc, xi, yi);
   float acc = 0.0f;
   int last = -1;
   for (;;) {
     int best = INT_MAX;
-    float be = 0.0f;
+    float be = 0.0f, bd = 0.0f;
     for (int ty = W.y0; ty <= W.y1; ++ty) {
       const int64_t t = ubase + (int64_t)ty * g.nx;
       const int s0 = a.tile_start[t + W.x0], s1 = a.tile_start[t + W.x1 + 1];
       for (int s = s0; s < s1; ++s) {
         const int hj = a.hs[s];
-        if (hj > last && hj < best && dist2(xi, yi, a.xs[s], a.ys[s]) < g.dc2) {
+        const float d2 = dist2(xi, yi, a.xs[s], a.ys[s]);
+        if (hj > last && hj < best && d2 < g.dc2) {
           best = hj;
           be = a.es[s];
+          bd = d2;
         }
       }
     }
     if (best == INT_MAX) break;
-    acc = __fadd_rn(acc, be);
+    acc = __fadd_rn(acc, kernel_term<K>(bd, g.ka, be));
     last = best;
   }
   return acc;
@@ -798,7 +863,7 @@ __device__ __forceinline__ int rec_key(const float4* rec, int j) { return __floa
 // indices into the records), so each query is one linear scan in ascending
 // hit index. Otherwise (or if the quads do not fit) a query merges its
 // window's tile lists itself.
-template <int MAXL>
+template <int MAXL, int K>
 __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, const Region& R, RegionLds& L, float4* rec,
                                                unsigned short* stile, unsigned short* qidx, bool keep) {
   const int per_row = R.rw + 1;
@@ -997,19 +1062,22 @@ __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, co
       for (; c + 3 < c1; c += 4) {
         const int i0 = qidx[c], i1 = qidx[c + 1], i2 = qidx[c + 2], i3 = qidx[c + 3];
         const float4 r0 = rec[i0], r1 = rec[i1], r2 = rec[i2], r3 = rec[i3];
-        const float a0 = __fadd_rn(rho, r0.z);
-        rho = dist2(xi, yi, r0.x, r0.y) < g.dc2 ? a0 : rho;
-        const float a1 = __fadd_rn(rho, r1.z);
-        rho = dist2(xi, yi, r1.x, r1.y) < g.dc2 ? a1 : rho;
-        const float a2 = __fadd_rn(rho, r2.z);
-        rho = dist2(xi, yi, r2.x, r2.y) < g.dc2 ? a2 : rho;
-        const float a3 = __fadd_rn(rho, r3.z);
-        rho = dist2(xi, yi, r3.x, r3.y) < g.dc2 ? a3 : rho;
+        const float d0 = dist2(xi, yi, r0.x, r0.y), d1 = dist2(xi, yi, r1.x, r1.y);
+        const float d2 = dist2(xi, yi, r2.x, r2.y), d3 = dist2(xi, yi, r3.x, r3.y);
+        const float a0 = __fadd_rn(rho, kernel_term<K>(d0, g.ka, r0.z));
+        rho = d0 < g.dc2 ? a0 : rho;
+        const float a1 = __fadd_rn(rho, kernel_term<K>(d1, g.ka, r1.z));
+        rho = d1 < g.dc2 ? a1 : rho;
+        const float a2 = __fadd_rn(rho, kernel_term<K>(d2, g.ka, r2.z));
+        rho = d2 < g.dc2 ? a2 : rho;
+        const float a3 = __fadd_rn(rho, kernel_term<K>(d3, g.ka, r3.z));
+        rho = d3 < g.dc2 ? a3 : rho;
       }
       for (; c < c1; ++c) {
         const float4 r = rec[qidx[c]];
-        const float a = __fadd_rn(rho, r.z);
-        rho = dist2(xi, yi, r.x, r.y) < g.dc2 ? a : rho;
+        const float d = dist2(xi, yi, r.x, r.y);
+        const float a = __fadd_rn(rho, kernel_term<K>(d, g.ka, r.z));
+        rho = d < g.dc2 ? a : rho;
       }
     } else if (ok) {
       int lo[MAXL * MAXL], hi[MAXL * MAXL];
@@ -1027,16 +1095,17 @@ __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, co
             hi[k] = 0;
           }
         }
-      rho = density_two_pass<MAXL>(rec, lo, hi, xi, yi, g.dc2);
+      rho = density_two_pass<MAXL, K>(rec, lo, hi, xi, yi, g.dc2, g.ka);
     } else {
       atomicOr(a.err, (uint32_t)E_WINDOW);
-      rho = density_global(g, a, ubase, xi, yi);
+      rho = density_global<K>(g, a, ubase, xi, yi);
     }
     a.rho[slot] = rho;
     if (keep) a.rho_out[__float_as_int(me.w)] = rho;
   }
 }
 
+template <int K>
 __device__ __forceinline__ void density_global_region(const Geom& g, const Arena& a, const Region& R, const RegionLds& L, bool keep) {
   const int64_t ubase = (int64_t)R.unit * g.tpl;
   const int nq = L.core_lo[R.ch];
@@ -1044,13 +1113,13 @@ __device__ __forceinline__ void density_global_region(const Geom& g, const Arena
     int row, p;
     core_query(L, R, q, row, p);
     const int slot = slot_of(L, row, p);
-    const float rho = density_global(g, a, ubase, a.xs[slot], a.ys[slot]);
+    const float rho = density_global<K>(g, a, ubase, a.xs[slot], a.ys[slot]);
     a.rho[slot] = rho;
     if (keep) a.rho_out[a.hs[slot]] = rho;
   }
 }
 
-template <bool G, int MAXL>
+template <bool G, int MAXL, int K>
 __global__ __launch_bounds__(kWG) void k_density(DescArg<G> dg, Geom g, Arena a) {
   const RunDesc d = dg.get();
   extern __shared__ __align__(16) unsigned char smem[];
@@ -1072,7 +1141,7 @@ __global__ __launch_bounds__(kWG) void k_density(DescArg<G> dg, Geom g, Arena a)
     region_setup(g, a, R, L);
     if (L.core_lo[R.ch] == 0) continue;
     if (R.total <= g.lds_cap) {
-      density_staged<MAXL>(g, a, R, L, rec, stile, qidx, keep);
+      density_staged<MAXL, K>(g, a, R, L, rec, stile, qidx, keep);
       continue;
     }
     // too dense: the four quarter blocks, then single tiles
@@ -1084,7 +1153,7 @@ __global__ __launch_bounds__(kWG) void k_density(DescArg<G> dg, Geom g, Arena a)
         region_setup(g, a, R, L);
         if (L.core_lo[R.ch] == 0) continue;
         if (R.total <= g.lds_cap) {
-          density_staged<MAXL>(g, a, R, L, rec, stile, qidx, keep);
+          density_staged<MAXL, K>(g, a, R, L, rec, stile, qidx, keep);
           continue;
         }
         for (int ty = sy; ty <= ey; ++ty)
@@ -1093,9 +1162,9 @@ __global__ __launch_bounds__(kWG) void k_density(DescArg<G> dg, Geom g, Arena a)
             region_setup(g, a, R, L);
             if (L.core_lo[R.ch] == 0) continue;
             if (R.total <= g.lds_cap)
-              density_staged<MAXL>(g, a, R, L, rec, stile, qidx, keep);
+              density_staged<MAXL, K>(g, a, R, L, rec, stile, qidx, keep);
             else
-              density_global_region(g, a, R, L, keep);
+              density_global_region<K>(g, a, R, L, keep);
           }
       }
   }
@@ -1586,10 +1655,22 @@ static hipError_t launch_all(const Geom& g, const Arena& a, DescArg<G> dg, const
   k_place<G><<<stream_grid(n), kWG, 0, s>>>(dg, g, a);
   mark();
   const int lds = lds_bytes_for(g);
-  if (g.maxl == 2)
-    k_density<G, 2><<<g_rho, kWG, lds, s>>>(dg, g, a);
-  else
-    k_density<G, 3><<<g_rho, kWG, lds, s>>>(dg, g, a);
+  if (g.kernel == 0) {
+    if (g.maxl == 2)
+      k_density<G, 2, 0><<<g_rho, kWG, lds, s>>>(dg, g, a);
+    else
+      k_density<G, 3, 0><<<g_rho, kWG, lds, s>>>(dg, g, a);
+  } else if (g.kernel == 1) {
+    if (g.maxl == 2)
+      k_density<G, 2, 1><<<g_rho, kWG, lds, s>>>(dg, g, a);
+    else
+      k_density<G, 3, 1><<<g_rho, kWG, lds, s>>>(dg, g, a);
+  } else {
+    if (g.maxl == 2)
+      k_density<G, 2, 2><<<g_rho, kWG, lds, s>>>(dg, g, a);
+    else
+      k_density<G, 3, 2><<<g_rho, kWG, lds, s>>>(dg, g, a);
+  }
   mark();
   if (g.flags & 4u)
     k_nearest_higher<G, true><<<g_nh, kWG, lds_bytes_nh(g), s>>>(dg, g, a);
@@ -1634,7 +1715,7 @@ int occupancy_blocks_per_cu(int which, int lds_bytes) {
   hipError_t e = hipSuccess;
   switch (which) {
     case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_hist<true>, kWG, 0); break;
-    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_density<true, 2>, kWG, lds_bytes); break;
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_density<true, 2, 0>, kWG, lds_bytes); break;
     case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_scan<true, SCAN_SEEDS_FOLLOW>, kWG, 0); break;
     case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_nearest_higher<true, false>, kWG, lds_bytes); break;
     default: break;

@@ -22,7 +22,8 @@ def gpu_run(ev, p, *, batched=False, n_events=1, flags=None, tuning=None, ctx=No
     if own:
         ctx = clue.Context(p["dc"], p["rho_c"], p["delta_c"], p["delta_o"], max_hits=max(n, 1),
                            max_events=max(n_events, 1), extent=p.get("extent"), bounds=p.get("bounds"),
-                           n_layers=p["n_layers"], flags=f)
+                           n_layers=p["n_layers"], flags=f, kernel=p.get("kernel", "flat"),
+                           kernel_scale=p.get("kernel_scale", 0.0))
     try:
         if tuning:
             ctx.set_tuning(**tuning)

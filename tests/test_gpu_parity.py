@@ -21,7 +21,8 @@ def _ref(ev, p, **kw):
     return oracle.run(ev["x"], ev["y"], ev["layer"], ev["energy"], dc=p["dc"], rho_c=p["rho_c"],
                       delta_c=p["delta_c"], delta_o=p["delta_o"], extent=p.get("extent"),
                       bounds=p.get("bounds"), n_layers=p["n_layers"], event=ev.get("event"),
-                      n_events=ev.get("n_events"), n_threads=NT, **kw)
+                      n_events=ev.get("n_events"), kernel=p.get("kernel", "flat"),
+                      kernel_scale=p.get("kernel_scale", 0.0), n_threads=NT, **kw)
 
 
 @pytest.mark.parametrize("case", CASES, ids=[c["name"] for c in CASES])
