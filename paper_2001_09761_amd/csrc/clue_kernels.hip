@@ -769,16 +769,18 @@ __device__ __forceinline__ float density_two_pass(const float4* __restrict__ rec
     }
   }
   if (big) return density_merge_full<MAXL, K>(rec, lo, hi, xi, yi, dc2, ka);
+  // heads of the lists; with the flat kernel the head's energy is kept,
+  // otherwise the selected head is re-read from LDS when it is added
   int hh[NL];
-  float ee[NL];
+  float ee[K == 0 ? NL : 1];
 #pragma unroll
   for (int k = 0; k < NL; ++k) {
     hh[k] = INT_MAX;
-    ee[k] = 0.0f;
+    if constexpr (K == 0) ee[k] = 0.0f;
     if (mlo[k] | mhi[k]) {
       const float4 r = rec[lo[k] + lowbit64(mlo[k], mhi[k])];
       hh[k] = __float_as_int(r.w);
-      ee[k] = kernel_term<K>(dist2(xi, yi, r.x, r.y), ka, r.z);
+      if constexpr (K == 0) ee[k] = r.z;
     }
   }
   float acc = 0.0f;
@@ -788,19 +790,25 @@ __device__ __forceinline__ float density_two_pass(const float4* __restrict__ rec
     for (int k = 1; k < NL; ++k) m = min(m, hh[k]);
     if (m == INT_MAX) break;
     // the selected list: take its head, drop its lowest passing bit
-    float e = ee[0];
+    float e = 0.0f;
+    if constexpr (K == 0) e = ee[0];
     unsigned ml = mlo[0], mh = mhi[0];
     int base = lo[0];
 #pragma unroll
     for (int k = 1; k < NL; ++k) {
       if (hh[k] == m) {
-        e = ee[k];
+        if constexpr (K == 0) e = ee[k];
         ml = mlo[k];
         mh = mhi[k];
         base = lo[k];
       }
     }
-    acc = __fadd_rn(acc, e);
+    if constexpr (K == 0) {
+      acc = __fadd_rn(acc, e);
+    } else {
+      const float4 rs = rec[base + lowbit64(ml, mh)];
+      acc = __fadd_rn(acc, kernel_term<K>(dist2(xi, yi, rs.x, rs.y), ka, rs.z));
+    }
     if (ml)
       ml &= ml - 1u;
     else
@@ -808,14 +816,13 @@ __device__ __forceinline__ float density_two_pass(const float4* __restrict__ rec
     const bool more = (ml | mh) != 0u;
     float4 r = make_float4(0.0f, 0.0f, 0.0f, __int_as_float(INT_MAX));
     if (more) r = rec[base + lowbit64(ml, mh)];
-    const float en = more ? kernel_term<K>(dist2(xi, yi, r.x, r.y), ka, r.z) : 0.0f;
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
       if (hh[k] == m) {
         mlo[k] = ml;
         mhi[k] = mh;
         hh[k] = __float_as_int(r.w);
-        ee[k] = en;
+        if constexpr (K == 0) ee[k] = r.z;
       }
     }
   }
