@@ -227,6 +227,26 @@ def main():
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
                 "alg_bytes_per_hit": ALG_BYTES[dom], "hits_per_launch": n, "avg_launch_ms": round(dom_ms, 4)}
+    # the Gaussian and exponential kernels of Eq. 3 on the same batch and tuning
+    kernels = {}
+    if not args.no_extras:
+        for kname, ks in (("gaussian", 1.0), ("exponential", 1.0)):
+            with clue.Context(params["dc"], params["rho_c"], params["delta_c"], params["delta_o"], max_hits=n,
+                              max_events=args.events, extent=params["extent"], n_layers=params["n_layers"],
+                              kernel=kname, kernel_scale=ks) as kctx:
+                kctx.set_tuning(tile_size=tuning["tile_size"], threads_per_query=tuning["threads_per_query"],
+                                block_x=tuning["block"][0], block_y=tuning["block"][1], lds_cap=tuning["lds_cap"],
+                                nh_first_radius=tuning["nh_first_radius"], density_quads=tuning["density_quads"])
+                krun = lambda: kctx.run_batch(d["event"], args.events, d["x"], d["y"], d["layer"], d["energy"],  # noqa: E731
+                                              cid, seed)
+                wall_k, _ = timed(krun, max(3, args.steps // 4), 2)
+                kctx.enable_stage_timing(True)
+                krun()
+                kst = kctx.stage_times()
+                kctx.status()
+            steps_k = max(3, args.steps // 4)
+            kernels[kname] = {"scale_cm": ks, "hits_per_s": round(n * steps_k / wall_k, 1),
+                              "density_ms": round(kst["density"], 4)}
     ctx.close()
     del d, cid, seed
 
@@ -251,6 +271,8 @@ def main():
         "roofline": roofline,
         "input_generation_s": round(t_gen, 2),
     }
+    if kernels:
+        out["density_kernels"] = kernels
 
     if not args.no_extras:
         out["host_resident"] = host_resident(events, params, log)
