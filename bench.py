@@ -236,7 +236,8 @@ def main():
                               kernel=kname, kernel_scale=ks) as kctx:
                 kctx.set_tuning(tile_size=tuning["tile_size"], threads_per_query=tuning["threads_per_query"],
                                 block_x=tuning["block"][0], block_y=tuning["block"][1], lds_cap=tuning["lds_cap"],
-                                nh_first_radius=tuning["nh_first_radius"], density_quads=tuning["density_quads"])
+                                nh_first_radius=tuning["nh_first_radius"], density_quads=tuning["density_quads"],
+                                expansion=tuning.get("expansion", 1))
                 krun = lambda: kctx.run_batch(d["event"], args.events, d["x"], d["y"], d["layer"], d["energy"],  # noqa: E731
                                               cid, seed)
                 wall_k, _ = timed(krun, max(3, args.steps // 4), 2)
@@ -247,6 +248,23 @@ def main():
             steps_k = max(3, args.steps // 4)
             kernels[kname] = {"scale_cm": ks, "hits_per_s": round(n * steps_k / wall_k, 1),
                               "density_ms": round(kst["density"], 4)}
+    # cluster expansion (Algorithm 3): pointer jumping against the k-way walk
+    # (one thread per seed) on the same batch, tuning otherwise unchanged
+    expansion = {}
+    if not args.no_extras:
+        for ex, label in ((1, "pointer_jumping"), (2, "k_way_dfs")):
+            ctx.set_tuning(expansion=ex)
+            steps_e = max(3, args.steps // 4)
+            wall_e, _ = timed(step_batched, steps_e, 2)
+            ctx.status()
+            same = bool(torch.equal(cid, ref_cid))
+            ctx.enable_stage_timing(True)
+            step_batched()
+            est = ctx.stage_times()
+            ctx.enable_stage_timing(False)
+            expansion[label] = {"hits_per_s": round(n * steps_e / wall_e, 1), "labels_ms": round(est["labels"], 4),
+                                "equals_headline": same}
+        ctx.set_tuning(expansion=tuning.get("expansion", 1))
     ctx.close()
     del d, cid, seed
 
@@ -273,11 +291,14 @@ def main():
     }
     if kernels:
         out["density_kernels"] = kernels
+    if expansion:
+        out["expansion"] = expansion
 
     if not args.no_extras:
         out["host_resident"] = host_resident(events, params, log)
         out.update(extras(args, params, log))
         out["paper_workload"] = paper_workload(log)
+        out["noise_sweep"] = noise_sweep(log)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(events, params)
     print(json.dumps(out), flush=True)
@@ -331,6 +352,34 @@ def traffic_summary(d, stage, n_events):
     with open(PROFILE_TRAFFIC, "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps(out))
+
+
+def noise_sweep(log):
+    """Noise rejection against delta_o (Fig. 4) on a stand-in for the figure's
+    data: 4000 unit-weight points in a 500 x 500 square, rho_c = 80,
+    delta_c = 40, delta_o in {10, 20, 60}. Noise is every hit with no cluster
+    (outliers and their descendant followers)."""
+    import numpy as np
+    import torch
+
+    import paper_2001_09761_amd as clue
+    from paper_2001_09761_amd import gen
+
+    ev, p = gen.noise_sweep_event()
+    dev = torch.device("cuda", 0)
+    t = {k: torch.from_numpy(v).to(dev) for k, v in ev.items() if isinstance(v, np.ndarray)}
+    rows = []
+    for do in gen.NOISE_SWEEP_DELTA_O:
+        with clue.Context(p["dc"], p["rho_c"], p["delta_c"], do, max_hits=ev["x"].size, extent=p["extent"],
+                          n_layers=1) as ctx:
+            cid, seed = ctx.run(t["x"], t["y"], t["layer"], t["energy"])
+            ctx.status()
+            c = cid.cpu().numpy()
+        rows.append({"delta_o": do, "noise_hits": int((c < 0).sum()), "seeds": int(seed.sum().item()),
+                     "noise_frac": round(float((c < 0).mean()), 4)})
+    log("noise sweep: " + ", ".join(f"delta_o={r['delta_o']:g}: {r['noise_hits']} noise" for r in rows))
+    return {"workload": f"{ev['x'].size} unit-weight points, 500x500, 7 elliptical clusters + 30% uniform noise",
+            "params": dict(gen.NOISE_SWEEP_PARAMS), "rows": rows}
 
 
 def paper_workload(log, batched_events=32):

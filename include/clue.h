@@ -205,6 +205,13 @@ typedef struct {
                                hit; 2: each hit merges its own window lists;
                                3: as 1, one lane merging each quad in order;
                                <= 0 keep */
+  int32_t expansion;        /* cluster-id propagation (Sec. 2.2, Algorithm 3):
+                               1: every hit follows nearest-higher links to its
+                               root (pointer jumping, n-way); 2: one thread per
+                               seed walks its follower tree depth first (k-way,
+                               as in the paper; builds the follower lists even
+                               with CLUE_NO_FOLLOWERS, and may grow the arena);
+                               <= 0 keep */
 } clue_tuning;
 
 /* Replace the tuning. Fields <= 0 keep their current value, except

@@ -1,8 +1,8 @@
 """Autotuner for the batched form.
 
 Sweeps the kernel tuning (tile size, tile-block shape, LDS budget, lanes per
-full-window nearest-higher query, first nearest-higher radius and the density
-strategy) by coordinate descent on a sample batch (repeated from the best
+full-window nearest-higher query, first nearest-higher radius, the density
+strategy and the cluster expansion) by coordinate descent on a sample batch (repeated from the best
 point while a sweep improves it, up to `sweeps` times), timing each candidate
 with HIP events on the run's stream. Every candidate must reproduce the
 reference cluster ids and seed flags bit for bit, or the tuner raises: the
@@ -36,6 +36,7 @@ def default_space(params):
         ("tile_size", [base_t, base_t * 1.125, base_t * 1.25, base_t * 1.5]),
         ("nh_first_radius", [0.25 * dm, 0.375 * dm, 0.5 * dm, 0.0]),
         ("threads_per_query", [1, 2, 4]),
+        ("expansion", [1, 2]),
     ]
 
 
@@ -95,7 +96,8 @@ def store_cached(key, tuning, path=DEFAULT_CACHE):
 def _apply(ctx, t):
     bx, by = t["block"]
     ctx.set_tuning(tile_size=t["tile_size"], threads_per_query=t["threads_per_query"], block_x=bx, block_y=by,
-                   lds_cap=t["lds_cap"], nh_first_radius=t["nh_first_radius"], density_quads=t["density_quads"])
+                   lds_cap=t["lds_cap"], nh_first_radius=t["nh_first_radius"], density_quads=t["density_quads"],
+                   expansion=t.get("expansion", 1))
 
 
 def autotune(ctx, batch, n_events, params, *, reps=3, space=None, stage_times=False, log=print, sweeps=2,
@@ -114,7 +116,8 @@ def autotune(ctx, batch, n_events, params, *, reps=3, space=None, stage_times=Fa
     cur = ctx.tuning()
     best = dict(tile_size=cur["tile_size"], threads_per_query=cur["threads_per_query"],
                 block=(cur["block_x"], cur["block_y"]), lds_cap=cur["lds_cap"],
-                nh_first_radius=cur["nh_first_radius"], density_quads=cur["density_quads"])
+                nh_first_radius=cur["nh_first_radius"], density_quads=cur["density_quads"],
+                expansion=cur["expansion"])
     run()
     torch.cuda.synchronize()
     ctx.status()

@@ -26,6 +26,7 @@ struct clue_ctx {
   int tpq = 1, bx = 8, by = 8, lds_cap = kDefaultLdsCap;
   float r1 = -1.0f;  // nearest-higher first radius; negative: default d_m / 4
   int quads = 1;      // density strategy (1 quads by search, 2 per-query merge, 3 quads by merge)
+  int expansion = 1;  // labels: 1 pointer jumping, 2 depth-first walk per seed
   LaunchCfg cfg{};
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -70,7 +71,7 @@ static inline bool finite(float v) { return std::isfinite(v); }
 // Geometry: tile size, halo and window bounds.
 // ---------------------------------------------------------------------------
 static int plan_geom(const clue_params& p, float tile, int tpq, int bx, int by, int lds_cap, float r1, int quads,
-                     Geom& g, std::string& msg) {
+                     int expansion, Geom& g, std::string& msg) {
   if (!finite(p.dc) || !(p.dc > 0.0f) || !finite(p.rho_c) || !finite(p.delta_c) || !finite(p.delta_o) ||
       p.delta_c < 0.0f || p.delta_o < 0.0f) {
     msg = "invalid clustering parameters (need finite dc > 0, rho_c, delta_c >= 0, delta_o >= 0)";
@@ -96,6 +97,10 @@ static int plan_geom(const clue_params& p, float tile, int tpq, int bx, int by, 
   }
   if (bx < 1 || by < 1 || bx > 16 || by > 16) {
     msg = "tile block must be within 1..16 tiles per side";
+    return CLUE_ERR_ARG;
+  }
+  if (expansion != 1 && expansion != 2) {
+    msg = "expansion must be 1 (pointer jumping) or 2 (depth-first per seed)";
     return CLUE_ERR_ARG;
   }
   if (lds_cap < 64 || lds_cap > kMaxLdsCap) {
@@ -137,6 +142,7 @@ static int plan_geom(const clue_params& p, float tile, int tpq, int bx, int by, 
   g.win_dm = (float)((double)dm * (1.0 + 1.0 / 1024.0));
   g.flags = p.flags;
   g.density_quads = quads == 2 ? 0 : (quads == 3 ? 2 : 1);
+  g.expand = expansion == 2 ? 1 : 0;
   // First nearest-higher pass: radius r1 (default d_m / 4); off when r1 <= 0
   // or r1 >= d_m.
   const float r1v = r1 < 0.0f ? 0.25f * dm : r1;
@@ -194,12 +200,12 @@ enum {
   A_FRANK, A_FLIST, A_RHO_OUT, A_NH_OUT, A_D2_OUT, A_STATUS, A_COUNTERS, A_ERR, A_DESC, A_NUM
 };
 
-static bool plan_arena(const Geom& g, uint32_t flags, int64_t N, int32_t E, ArenaPlan& P) {
+static bool plan_arena(const Geom& g, int64_t N, int32_t E, ArenaPlan& P) {
   const int64_t tiles = (int64_t)E * g.L * g.tpl + 1;
   if (tiles >= ((int64_t)1 << 31) || N >= ((int64_t)1 << 31) - 1) return false;
   const int64_t chunks = std::max<int64_t>((tiles + kScanChunk - 1) / kScanChunk, (N + 1 + kScanChunk - 1) / kScanChunk);
-  const bool fol = !(flags & CLUE_NO_FOLLOWERS);
-  const bool keep = flags & CLUE_KEEP_INTERMEDIATES;
+  const bool fol = builds_lists(g);
+  const bool keep = g.flags & CLUE_KEEP_INTERMEDIATES;
   size_t sz[A_NUM];
   const size_t n = (size_t)std::max<int64_t>(N, 1);
   sz[A_KEY] = 4 * n;
@@ -233,7 +239,7 @@ static bool plan_arena(const Geom& g, uint32_t flags, int64_t N, int32_t E, Aren
 static void bind_arena(clue_ctx* c, const ArenaPlan& P, int64_t N, int32_t E) {
   char* b = (char*)c->arena_base;
   Arena& a = c->a;
-  const bool fol = !(c->params.flags & CLUE_NO_FOLLOWERS);
+  const bool fol = builds_lists(c->g);
   const bool keep = c->params.flags & CLUE_KEEP_INTERMEDIATES;
   a.key = (int32_t*)(b + P.off[A_KEY]);
   a.rank = (int32_t*)(b + P.off[A_RANK]);
@@ -285,7 +291,7 @@ static void compute_cfg(clue_ctx* c) {
 // (Re)allocates the arena for (N, E) under the current geometry.
 static int alloc_arena(clue_ctx* c, int64_t N, int32_t E) {
   ArenaPlan P;
-  if (!plan_arena(c->g, c->params.flags, N, E, P))
+  if (!plan_arena(c->g, N, E, P))
     return set_err(c, CLUE_ERR_CAPACITY, "capacity exceeds 32-bit index limits (hits or tiles)");
   if (c->budget && P.total > c->budget)
     return set_err(c, CLUE_ERR_BUDGET, "arena of " + std::to_string(P.total) + " bytes exceeds the HBM budget");
@@ -346,10 +352,10 @@ int clue_footprint_bytes(const clue_params* p, int64_t max_hits, int32_t max_eve
   Geom g{};
   std::string msg;
   const int tpq = p->threads_per_query > 0 ? p->threads_per_query : 1;
-  int rc = plan_geom(*p, p->tile_size, tpq, 8, 8, kDefaultLdsCap, -1.0f, 1, g, msg);
+  int rc = plan_geom(*p, p->tile_size, tpq, 8, 8, kDefaultLdsCap, -1.0f, 1, 1, g, msg);
   if (rc != CLUE_OK) return rc;
   ArenaPlan P;
-  if (!plan_arena(g, p->flags, max_hits, max_events, P)) return CLUE_ERR_CAPACITY;
+  if (!plan_arena(g, max_hits, max_events, P)) return CLUE_ERR_CAPACITY;
   *bytes_out = P.total;
   return CLUE_OK;
 }
@@ -369,7 +375,8 @@ int clue_create(clue_ctx** out, const clue_params* p, int hip_device, int64_t ma
   c->tpq = p->threads_per_query > 0 ? p->threads_per_query : 1;
   c->tile = p->tile_size;
   std::string msg;
-  int rc = plan_geom(c->params, c->tile, c->tpq, c->bx, c->by, c->lds_cap, c->r1, c->quads, c->g, msg);
+  int rc = plan_geom(c->params, c->tile, c->tpq, c->bx, c->by, c->lds_cap, c->r1, c->quads, c->expansion, c->g,
+                     msg);
   if (rc != CLUE_OK) {
     set_err(nullptr, rc, msg);
     delete c;
@@ -695,6 +702,7 @@ int clue_status(clue_ctx* c, void* stream) {
   }
   if (err & E_INPUT) return set_err(c, CLUE_ERR_INPUT, "invalid hit data");
   if (err & E_WINDOW) return set_err(c, CLUE_ERR_DEVICE, "a query window left its staged halo");
+  if (err & E_WALK) return set_err(c, CLUE_ERR_DEVICE, "a cluster expansion walk exceeded its step bound");
   return CLUE_OK;
 }
 
@@ -708,11 +716,13 @@ int clue_set_tuning(clue_ctx* c, const clue_tuning* t) {
   const int cap = t->lds_cap > 0 ? t->lds_cap : c->lds_cap;
   const float r1 = t->nh_first_radius >= 0.0f ? t->nh_first_radius : c->r1;
   const int quads = t->density_quads > 0 ? t->density_quads : c->quads;
-  int rc = plan_geom(c->params, tile, tpq, bx, by, cap, r1, quads, g, msg);
+  const int expansion = t->expansion > 0 ? t->expansion : c->expansion;
+  int rc = plan_geom(c->params, tile, tpq, bx, by, cap, r1, quads, expansion, g, msg);
   if (rc != CLUE_OK) return set_err(c, rc, msg);
   HIP_TRY(c, hipSetDevice(c->device));
   HIP_TRY(c, hipDeviceSynchronize());
-  const bool regrow = (int64_t)c->a.cap_events * g.L * g.tpl + 1 > c->a.cap_tiles;
+  const bool regrow =
+      (int64_t)c->a.cap_events * g.L * g.tpl + 1 > c->a.cap_tiles || (builds_lists(g) && !c->a.flist);
   const Geom old = c->g;
   c->g = g;
   drop_graph(c);
@@ -732,6 +742,7 @@ int clue_set_tuning(clue_ctx* c, const clue_tuning* t) {
   c->lds_cap = cap;
   c->r1 = r1;
   c->quads = quads;
+  c->expansion = expansion;
   return CLUE_OK;
 }
 
@@ -745,6 +756,7 @@ int clue_get_tuning(const clue_ctx* c, clue_tuning* t, int32_t* halo) {
     t->lds_cap = c->g.lds_cap;
     t->nh_first_radius = c->g.nh_phase1 ? std::sqrt(c->g.r1sq) : 0.0f;
     t->density_quads = c->g.density_quads == 0 ? 2 : (c->g.density_quads == 2 ? 3 : 1);
+    t->expansion = c->g.expand ? 2 : 1;
   }
   if (halo) *halo = c->g.halo;
   return CLUE_OK;

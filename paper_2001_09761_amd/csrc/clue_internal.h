@@ -37,6 +37,7 @@ enum Counter {
 enum ErrBits : uint32_t {
   E_INPUT = 1u,    // non-finite coordinate/energy, bad layer or event id
   E_WINDOW = 2u,   // a query window left the staged halo (never expected)
+  E_WALK = 4u,     // an expansion walk exceeded its step bound (never expected)
 };
 
 // Per-run descriptor: sizes and the caller's buffers.
@@ -82,18 +83,27 @@ struct Geom {
   int32_t nh_phase1;  // nearest-higher first searches radius r1 < dm
   float r1sq;       // fl(r1*r1)
   float win_r1;     // r1 (1 + 2^-10)
+  int32_t expand;   // cluster expansion: 0 pointer jumping, 1 depth-first from each seed
   uint32_t flags;   // CLUE_* flags
 };
+
+// Follower lists (counts, ranks, CSR) are built when the caller asks for them
+// or when the depth-first expansion walks them.
+__host__ __device__ inline bool builds_lists(const Geom& g) { return !(g.flags & 8u) || g.expand != 0; }
 
 // Arena: device scratch owned by a context.
 struct Arena {
   int32_t* key;          // [N]   caller order: global tile id of each hit
   int32_t* rank;         // [N]   caller order: arrival rank within its tile
+                         //       (the depth-first expansion reuses both for each
+                         //       follower's owner and its position in the owner's list)
                          //       (the grid build keeps arrival-order hit ids and tiles
                          //       in the rho and parent buffers until each tile is
                          //       ordered by hit index)
   int32_t* tile_start;   // [TT+1] tile counts, scanned in place into CSR offsets
-  float* xs;             // [N]   slot order (tile CSR; hit index ascending within a tile)
+  float* xs;             // [N]   slot order (tile CSR; hit index ascending within a tile);
+                         //       after the nearest-higher stage, the depth-first
+                         //       expansion's seed list
   float* ys;
   float* es;
   int32_t* hs;           // [N]   slot -> caller (batch-global) hit index

@@ -15,6 +15,8 @@
 //   k_label            cluster ids: each hit follows nearest-higher links of
 //                      followers to its root (pointer jumping with path
 //                      compression); registers follower-list entries
+//   k_expand_init      the k-way alternative to k_label (Algorithm 3): follower
+//   k_expand_dfs       lists, seed list, then one depth-first walk per seed
 //   k_follow_sort      sorts each follower list by hit index, event-local ids
 //
 // Every float operation that decides a result is an explicit round-to-nearest
@@ -97,7 +99,7 @@ __global__ __launch_bounds__(kWG) void k_clear(DescArg<G> dg, Geom g, Arena a) {
   const RunDesc d = dg.get();
   const int64_t tt = (int64_t)d.n_events * g.L * g.tpl + 1;
   const int64_t n1 = (int64_t)d.n + 1;
-  const bool fol = !(g.flags & 8u);
+  const bool fol = builds_lists(g);
   const int64_t stride = (int64_t)gridDim.x * kWG;
   const int64_t i0 = (int64_t)blockIdx.x * kWG + threadIdx.x;
   for (int64_t i = i0; i < tt; i += stride) a.tile_start[i] = 0;
@@ -1243,7 +1245,7 @@ __device__ __forceinline__ void decide_and_store(const Geom& g, const Arena& a, 
   a.parent[slot] = follower ? b.p : slot;
   a.flags[slot] = (uint8_t)((seed ? F_SEED : 0) | (outlier ? F_OUTLIER : 0) | (follower ? F_FOLLOWER : 0));
   d.is_seed[hi] = seed ? 1 : 0;
-  if (follower && !(g.flags & 8u)) a.frank[slot] = atomicAdd(&a.fstart[b.h()], 1);
+  if (follower && builds_lists(g)) a.frank[slot] = atomicAdd(&a.fstart[b.h()], 1);
   if (g.flags & 2u) {
     a.nh_out[hi] = has ? b.h() - ev_first : -1;
     a.d2_out[hi] = d2;
@@ -1473,7 +1475,7 @@ __global__ __launch_bounds__(kWG) void k_nearest_higher(DescArg<G> dg, Geom g, A
 template <bool G>
 __global__ __launch_bounds__(kWG) void k_label(DescArg<G> dg, Geom g, Arena a) {
   const RunDesc d = dg.get();
-  const bool fol = !(g.flags & 8u);
+  const bool fol = builds_lists(g);
   constexpr int U = kPlaceU;  // hits per lane per step, their chases interleaved
   const int stride = gridDim.x * kWG * U;
   for (int sb = blockIdx.x * kWG * U + (int)threadIdx.x; sb < d.n; sb += stride) {
@@ -1529,6 +1531,108 @@ __global__ __launch_bounds__(kWG) void k_label(DescArg<G> dg, Geom g, Arena a) {
         lab = a.seed_rank[a.hs[r[j]]] - a.seed_rank[event_first_hit(a, d, e)];
       }
       d.cluster_id[hsj[j]] = lab;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Labels by k-way expansion (Sec. 2.2, Algorithm 3): one thread per seed walks
+// the seed's follower tree depth first and gives every hit in it the seed's
+// cluster id. The walk keeps no stack: each follower's owner and its position
+// in the owner's list (key / rank, free after the grid build) lead back up to
+// the next unvisited sibling, so a thread holds O(1) state whatever the tree's
+// depth.
+// ---------------------------------------------------------------------------
+
+// Part 1: places follower-list entries (as k_label does), records owner and
+// position per follower, labels seeds with their number within the event and
+// every other hit -1, and lists the seeds by rank.
+template <bool G>
+__global__ __launch_bounds__(kWG) void k_expand_init(DescArg<G> dg, Geom g, Arena a) {
+  const RunDesc d = dg.get();
+  int* const seeds = reinterpret_cast<int*>(a.xs);
+  constexpr int U = kPlaceU;
+  const int stride = gridDim.x * kWG * U;
+  for (int sb = blockIdx.x * kWG * U + (int)threadIdx.x; sb < d.n; sb += stride) {
+    int p[U], h[U];
+    unsigned f[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      const int s = sb + j * kWG;
+      f[j] = 0;
+      p[j] = 0;
+      h[j] = 0;
+      if (s < d.n) {
+        f[j] = a.flags[s] | 0x100u;
+        p[j] = a.parent[s];
+        h[j] = a.hs[s];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      if (!(f[j] & 0x100u)) continue;
+      const int s = sb + j * kWG;
+      int lab = -1;
+      if (f[j] & F_FOLLOWER) {
+        const int owner = a.hs[p[j]];
+        const int r = a.frank[s];
+        a.flist[a.fstart[owner] + r] = h[j];
+        a.key[h[j]] = owner;
+        a.rank[h[j]] = r;
+      } else if (f[j] & F_SEED) {
+        const int e = d.event ? clampi(d.event[h[j]] - d.event_base, 0, d.n_events - 1) : 0;
+        const int rk = a.seed_rank[h[j]];
+        lab = rk - a.seed_rank[event_first_hit(a, d, e)];
+        seeds[rk] = h[j];
+      }
+      d.cluster_id[h[j]] = lab;
+    }
+  }
+}
+
+// Part 2: the walks. Each visits its tree in preorder: down to a node's first
+// follower, else up through owners to the first one with a next sibling. A
+// walk takes at most 2 (n + 1) steps (each edge down once and up once); a walk
+// that reached that bound would mean corrupt lists, so it stops and flags the
+// run instead of looping.
+template <bool G>
+__global__ __launch_bounds__(kWG) void k_expand_dfs(DescArg<G> dg, Geom g, Arena a) {
+  const RunDesc d = dg.get();
+  const int* const seeds = reinterpret_cast<const int*>(a.xs);
+  const int ns = a.seed_rank[d.n];
+  const int64_t max_steps = 2 * ((int64_t)d.n + 1);
+  for (int t = blockIdx.x * kWG + (int)threadIdx.x; t < ns; t += gridDim.x * kWG) {
+    const int root = seeds[t];
+    const int lab = d.cluster_id[root];
+    int u = root;
+    int b = a.fstart[u], e = a.fstart[u + 1];
+    int64_t steps = 0;
+    for (;;) {
+      if (++steps > max_steps) {
+        atomicOr(a.err, (uint32_t)E_WALK);
+        break;
+      }
+      if (b < e) {
+        u = a.flist[b];  // first follower
+      } else {
+        // climb to the nearest node (u or an ancestor) that has a next sibling
+        bool found = false;
+        while (u != root && steps <= max_steps) {
+          ++steps;
+          const int p = a.key[u];
+          const int nx = a.fstart[p] + a.rank[u] + 1;
+          if (nx < a.fstart[p + 1]) {
+            u = a.flist[nx];
+            found = true;
+            break;
+          }
+          u = p;
+        }
+        if (!found) break;
+      }
+      d.cluster_id[u] = lab;
+      b = a.fstart[u];
+      e = a.fstart[u + 1];
     }
   }
 }
@@ -1684,12 +1788,18 @@ static hipError_t launch_all(const Geom& g, const Arena& a, DescArg<G> dg, const
   else
     k_nearest_higher<G, false><<<g_nh, kWG, lds_bytes_nh(g), s>>>(dg, g, a);
   mark();
-  if (fol)
+  if (builds_lists(g))
     k_scan<G, SCAN_SEEDS_FOLLOW><<<g_scan_s, kWG, 0, s>>>(dg, g, a);
   else
     k_scan<G, SCAN_SEEDS><<<g_scan_s, kWG, 0, s>>>(dg, g, a);
   mark();
-  k_label<G><<<stream_grid(cdiv(n, kPlaceU)), kWG, 0, s>>>(dg, g, a);
+  if (g.expand) {
+    k_expand_init<G><<<stream_grid(cdiv(n, kPlaceU)), kWG, 0, s>>>(dg, g, a);
+    const int g_dfs = G ? cfg.persist_blocks_stream : std::min(stream_grid(n), std::max(1, cfg.persist_blocks_stream));
+    k_expand_dfs<G><<<g_dfs, kWG, 0, s>>>(dg, g, a);
+  } else {
+    k_label<G><<<stream_grid(cdiv(n, kPlaceU)), kWG, 0, s>>>(dg, g, a);
+  }
   mark();
   if (fol) k_follow_sort<G><<<stream_grid(cdiv(n, kPlaceU)), kWG, 0, s>>>(dg, g, a);
   mark();

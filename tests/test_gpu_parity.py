@@ -66,6 +66,8 @@ TUNINGS = [
     dict(nh_first_radius=0.5, threads_per_query=2),
     dict(nh_first_radius=3.99),
     dict(lds_cap=2048, block_x=16, block_y=16),
+    dict(expansion=2),                        # k-way expansion: one thread per seed
+    dict(expansion=2, lds_cap=64, threads_per_query=4),
 ]
 
 

@@ -123,3 +123,28 @@ def test_delta_o_monotone_noise():
         if prev_noise is not None:
             assert np.all(noise <= prev_noise)
         prev_noise = noise
+
+
+def test_delta_o_sweep_fig4_stand_in():
+    """P8 past delta_c (Fig. 4's delta_o = 60 > delta_c = 40): raising delta_o
+    with rho_c, delta_c and dc fixed keeps every nearest-higher found within
+    the smaller d_m (the nearest higher hit is the nearest whatever the
+    radius), so seeds stay seeds, followers stay followers, and only outliers
+    can be demoted to followers. Hence the seeds, and every clustered hit's
+    id, are unchanged, and the noise set only shrinks. On this data it
+    shrinks strictly at each of the figure's three values."""
+    ev, p = gen.noise_sweep_event()
+    prev = None
+    counts = []
+    for do in (5.0,) + gen.NOISE_SWEEP_DELTA_O + (100.0,):
+        o = oracle.run(ev["x"], ev["y"], ev["layer"], ev["energy"], dc=p["dc"], rho_c=p["rho_c"],
+                       delta_c=p["delta_c"], delta_o=do, extent=p["extent"], n_layers=1)
+        cid = o["cluster_id"]
+        if prev is not None:
+            assert np.array_equal(o["is_seed"], prev["is_seed"])
+            kept = prev["cluster_id"] >= 0
+            assert np.array_equal(cid[kept], prev["cluster_id"][kept])
+            assert np.all((cid < 0) <= (prev["cluster_id"] < 0))
+        counts.append(int((cid < 0).sum()))
+        prev = o
+    assert counts[0] > counts[1] > counts[2] > counts[3] >= counts[4], counts
