@@ -92,6 +92,23 @@ __device__ __forceinline__ int event_first_hit(const Arena& a, const RunDesc& d,
 }
 
 // ---------------------------------------------------------------------------
+// Streaming kernels cut their index range into chunks of `chunk` consecutive
+// indices and give each XCD one contiguous run of chunks (workgroups are
+// dispatched to the XCDs round-robin by id; the grid is a multiple of
+// kQueues). Neighbouring indices share lines in the gathers and scattered
+// writes that follow, so they are fetched into, and completed in, one L2.
+// ---------------------------------------------------------------------------
+struct ChunkRun {
+  int c, end, step;
+};
+__device__ __forceinline__ ChunkRun xcd_run(int n, int chunk) {
+  const int nch = (int)(((int64_t)n + chunk - 1) / chunk);
+  const int x = (int)blockIdx.x % kQueues, i = (int)blockIdx.x / kQueues;
+  return {(int)((int64_t)nch * x / kQueues) + i, (int)((int64_t)nch * (x + 1) / kQueues),
+          (int)gridDim.x / kQueues};
+}
+
+// ---------------------------------------------------------------------------
 // k_clear
 // ---------------------------------------------------------------------------
 template <bool G>
@@ -124,9 +141,9 @@ template <bool G>
 __global__ __launch_bounds__(kWG) void k_hist(DescArg<G> dg, Geom g, Arena a) {
   const RunDesc d = dg.get();
   constexpr int U = kPlaceU;  // sub-batches per step; their atomics overlap
-  const int stride = gridDim.x * kWG * U;
   const int lane = threadIdx.x & 63;
-  for (int h0 = blockIdx.x * kWG * U; h0 < d.n; h0 += stride) {  // uniform per workgroup
+  for (ChunkRun r = xcd_run(d.n, kWG * U); r.c < r.end; r.c += r.step) {
+    const int h0 = r.c * kWG * U;  // uniform per workgroup
     int t[U];
 #pragma unroll
     for (int j = 0; j < U; ++j) {
@@ -198,8 +215,8 @@ __global__ __launch_bounds__(kWG) void k_scatter(DescArg<G> dg, Geom g, Arena a)
   const RunDesc d = dg.get();
   int* ids = reinterpret_cast<int*>(a.rho);
   constexpr int U = kPlaceU;
-  const int stride = gridDim.x * kWG * U;
-  for (int h0 = blockIdx.x * kWG * U + (int)threadIdx.x; h0 < d.n; h0 += stride) {
+  for (ChunkRun rn = xcd_run(d.n, kWG * U); rn.c < rn.end; rn.c += rn.step) {
+    const int h0 = rn.c * kWG * U + (int)threadIdx.x;
     int t[U], r[U];
 #pragma unroll
     for (int j = 0; j < U; ++j) {
@@ -225,8 +242,9 @@ template <bool G>
 __global__ __launch_bounds__(kWG) void k_place(DescArg<G> dg, Geom g, Arena a) {
   const RunDesc d = dg.get();
   const int* ids = reinterpret_cast<const int*>(a.rho);
-  const int stride = gridDim.x * kWG;
-  for (int s = blockIdx.x * kWG + threadIdx.x; s < d.n; s += stride) {
+  for (ChunkRun rn = xcd_run(d.n, kWG); rn.c < rn.end; rn.c += rn.step) {
+    const int s = rn.c * kWG + (int)threadIdx.x;
+    if (s >= d.n) continue;
     const int h = ids[s];
     const int t = a.parent[s];
     const float x = d.x[h], y = d.y[h], e = d.e[h];
@@ -1477,8 +1495,8 @@ __global__ __launch_bounds__(kWG) void k_label(DescArg<G> dg, Geom g, Arena a) {
   const RunDesc d = dg.get();
   const bool fol = builds_lists(g);
   constexpr int U = kPlaceU;  // hits per lane per step, their chases interleaved
-  const int stride = gridDim.x * kWG * U;
-  for (int sb = blockIdx.x * kWG * U + (int)threadIdx.x; sb < d.n; sb += stride) {
+  for (ChunkRun rn = xcd_run(d.n, kWG * U); rn.c < rn.end; rn.c += rn.step) {
+    const int sb = rn.c * kWG * U + (int)threadIdx.x;
     int s[U], p0[U], hsj[U], r[U], p[U];
     unsigned f[U];
     bool v[U];
@@ -1552,8 +1570,8 @@ __global__ __launch_bounds__(kWG) void k_expand_init(DescArg<G> dg, Geom g, Aren
   const RunDesc d = dg.get();
   int* const seeds = reinterpret_cast<int*>(a.xs);
   constexpr int U = kPlaceU;
-  const int stride = gridDim.x * kWG * U;
-  for (int sb = blockIdx.x * kWG * U + (int)threadIdx.x; sb < d.n; sb += stride) {
+  for (ChunkRun rn = xcd_run(d.n, kWG * U); rn.c < rn.end; rn.c += rn.step) {
+    const int sb = rn.c * kWG * U + (int)threadIdx.x;
     int p[U], h[U];
     unsigned f[U];
 #pragma unroll
@@ -1646,8 +1664,8 @@ template <bool G>
 __global__ __launch_bounds__(kWG) void k_follow_sort(DescArg<G> dg, Geom g, Arena a) {
   const RunDesc d = dg.get();
   constexpr int U = kPlaceU;
-  const int stride = gridDim.x * kWG * U;
-  for (int hb = blockIdx.x * kWG * U + (int)threadIdx.x; hb < d.n; hb += stride) {
+  for (ChunkRun rn = xcd_run(d.n, kWG * U); rn.c < rn.end; rn.c += rn.step) {
+    const int hb = rn.c * kWG * U + (int)threadIdx.x;
     int b[U], end[U];
 #pragma unroll
     for (int j = 0; j < U; ++j) {
@@ -1739,9 +1757,11 @@ static hipError_t launch_all(const Geom& g, const Arena& a, DescArg<G> dg, const
   const int64_t n = host_d.n;
   const int64_t tt = (int64_t)host_d.n_events * g.L * g.tpl + 1;
   const int64_t items = (int64_t)host_d.n_events * g.L * g.bpu;
+  // streaming grids are a multiple of kQueues (one run of chunks per XCD)
   auto stream_grid = [&](int64_t work) {
     if (G) return cfg.persist_blocks_stream;
-    return (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(work, kWG), 1 << 20));
+    const int64_t b = std::max<int64_t>(1, std::min<int64_t>(cdiv(work, kWG), 1 << 20));
+    return (int)((b + kQueues - 1) / kQueues * kQueues);
   };
   const int g_clear = G ? cfg.persist_blocks_stream
                         : (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(std::max(tt, n + 1), kWG), 1 << 16));
