@@ -883,11 +883,18 @@ __device__ __forceinline__ float density_global(const Geom& g, const Arena& a, i
 // Hit index of an LDS record.
 __device__ __forceinline__ int rec_key(const float4* rec, int j) { return __float_as_int(rec[j].w); }
 
+// Quad-list entries are byte offsets of records (a staged position times 16,
+// below 2^15 for every LDS cap), so a scan adds no index scaling.
+__device__ __forceinline__ float4 rec_at(const float4* rec, int byte_off) {
+  return *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(rec) + byte_off);
+}
+static_assert(kMaxLdsCap * 16 <= 65536, "quad-list byte offsets are 16-bit");
+
 // Density over a staged region (records x, y, E, index; each tile in
 // ascending hit index). With MAXL == 2 every query window lies inside the
 // 2x2 tile quad anchored at its lower-left window tile; the quads a core
-// query can use are merged once per region into index-ordered lists (LDS
-// indices into the records), so each query is one linear scan in ascending
+// query can use are merged once per region into index-ordered lists (byte
+// offsets of the records), so each query is one linear scan in ascending
 // hit index. Otherwise (or if the quads do not fit) a query merges its
 // window's tile lists itself.
 template <int MAXL, int K>
@@ -973,7 +980,7 @@ __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, co
         const bool s0 = key[0] == m, s1 = !s0 && key[1] == m, s2 = !s0 && !s1 && key[2] == m;
         const int pk = s0 ? cur[0] : (s1 ? cur[1] : (s2 ? cur[2] : cur[3]));
         const int ek = s0 ? end[0] : (s1 ? end[1] : (s2 ? end[2] : end[3]));
-        qidx[out + i] = (unsigned short)pk;
+        qidx[out + i] = (unsigned short)(pk * (int)sizeof(float4));
         const int np = pk + 1;
         const int nk = np < ek ? rec_key(rec, np) : INT_MAX;
         const bool s3 = !s0 && !s1 && !s2;
@@ -1063,7 +1070,7 @@ __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, co
 #pragma unroll
             for (int ox = -dx; ox <= 1 - dx; ++ox)
               if (ox != 0 || oy != 0) pos += below[(oy + 1) * 3 + ox + 1];
-          qidx[L.qoff[(tr - dy - qy0) * qw + (tc - dx - qx0)] + pos] = (unsigned short)p;
+          qidx[L.qoff[(tr - dy - qy0) * qw + (tc - dx - qx0)] + pos] = (unsigned short)(p * (int)sizeof(float4));
         }
     }
     __syncthreads();
@@ -1083,12 +1090,13 @@ __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, co
     float rho = 0.0f;
     if (ok && use_quads) {
       const int qq = (ty0 - qy0) * qw + (tx0 - qx0);
-      const int c1 = L.qoff[qq + 1];
-      int c = L.qoff[qq];
+      const unsigned short* qp = qidx + L.qoff[qq];
+      const unsigned short* const qe = qidx + L.qoff[qq + 1];
+      const unsigned short* const qe4 = qe - 3;
       // loads batched four at a time; additions stay in ascending index order
-      for (; c + 3 < c1; c += 4) {
-        const int i0 = qidx[c], i1 = qidx[c + 1], i2 = qidx[c + 2], i3 = qidx[c + 3];
-        const float4 r0 = rec[i0], r1 = rec[i1], r2 = rec[i2], r3 = rec[i3];
+      for (; qp < qe4; qp += 4) {
+        const int i0 = qp[0], i1 = qp[1], i2 = qp[2], i3 = qp[3];
+        const float4 r0 = rec_at(rec, i0), r1 = rec_at(rec, i1), r2 = rec_at(rec, i2), r3 = rec_at(rec, i3);
         const float d0 = dist2(xi, yi, r0.x, r0.y), d1 = dist2(xi, yi, r1.x, r1.y);
         const float d2 = dist2(xi, yi, r2.x, r2.y), d3 = dist2(xi, yi, r3.x, r3.y);
         const float a0 = __fadd_rn(rho, kernel_term<K>(d0, g.ka, r0.z));
@@ -1100,8 +1108,8 @@ __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, co
         const float a3 = __fadd_rn(rho, kernel_term<K>(d3, g.ka, r3.z));
         rho = d3 < g.dc2 ? a3 : rho;
       }
-      for (; c < c1; ++c) {
-        const float4 r = rec[qidx[c]];
+      for (; qp < qe; ++qp) {
+        const float4 r = rec_at(rec, *qp);
         const float d = dist2(xi, yi, r.x, r.y);
         const float a = __fadd_rn(rho, kernel_term<K>(d, g.ka, r.z));
         rho = d < g.dc2 ? a : rho;
@@ -1221,21 +1229,26 @@ __device__ __forceinline__ unsigned long long key64(unsigned hi, unsigned lo) {
 }
 
 struct NhBest {
-  unsigned long long k;  // (d2 bits, caller index); ~0: none
+  unsigned long long k;  // (d2 bits, caller index) of the best so far
   int p;                 // LDS position >= 0, or global slot s encoded as -2 - s; -1 none
   __device__ __forceinline__ float d2() const { return __uint_as_float((unsigned)(k >> 32)); }
   __device__ __forceinline__ int h() const { return (int)(unsigned)(k & 0xffffffffu); }
 };
 
-// One candidate j for query i: eligible when d2 < thr and j is higher
-// (ordr/h keys); keeps the lexicographic minimum of (d2, index). d2 >= 0,
-// so its bit pattern orders like its value.
+// Search state before any candidate, for the squared radius thr: the key
+// (thr, 0) is beaten exactly by the keys (d2, index) with d2 < thr, so the
+// radius test needs no comparison of its own.
+__device__ __forceinline__ NhBest nh_start(float thr) { return NhBest{key64(__float_as_uint(thr), 0u), -1}; }
+
+// One candidate j for query i: eligible when j is higher (ord/index keys);
+// keeps the lexicographic minimum of (d2, index), which starts at
+// nh_start(thr). d2 >= 0, so its bit pattern orders like its value.
 template <bool STRICT>
 __device__ __forceinline__ void nh_consider(NhBest& b, float d2, unsigned ordj, unsigned hj, int pq, unsigned ordi,
-                                            unsigned hi, float thr) {
+                                            unsigned hi) {
   const bool higher = STRICT ? ordj > ordi : key64(ordj, hj) > key64(ordi, hi);
   const unsigned long long ck = key64(__float_as_uint(d2), hj);
-  const bool take = (d2 < thr) & higher & (ck < b.k);  // branch-free select
+  const bool take = higher & (ck < b.k);  // branch-free select
   b.k = take ? ck : b.k;
   b.p = take ? pq : b.p;
 }
@@ -1275,26 +1288,26 @@ __device__ __forceinline__ void decide_and_store(const Geom& g, const Arena& a, 
 template <bool STRICT>
 __device__ __forceinline__ void nh_scan_staged(const float4* __restrict__ rec, const int* ts, int per_row,
                                                int tx0, int tx1, int ty0, int ty1, int sub, int step, float xi,
-                                               float yi, unsigned ordi, unsigned hi, float thr, NhBest& b) {
+                                               float yi, unsigned ordi, unsigned hi, NhBest& b) {
   for (int ty = ty0; ty <= ty1; ++ty) {
     const int q0 = ts[ty * per_row + tx0];
     const int q1 = ts[ty * per_row + tx1 + 1];
     int c = q0 + sub;
+    const int c4 = q1 - 3 * step;
     // four independent LDS loads in flight per step
-    for (; c + 3 * step < q1; c += 4 * step) {
+    for (; c < c4; c += 4 * step) {
       const float4 r0 = rec[c], r1 = rec[c + step], r2 = rec[c + 2 * step], r3 = rec[c + 3 * step];
-      nh_consider<STRICT>(b, dist2(xi, yi, r0.x, r0.y), __float_as_uint(r0.w), __float_as_uint(r0.z), c, ordi, hi,
-                          thr);
+      nh_consider<STRICT>(b, dist2(xi, yi, r0.x, r0.y), __float_as_uint(r0.w), __float_as_uint(r0.z), c, ordi, hi);
       nh_consider<STRICT>(b, dist2(xi, yi, r1.x, r1.y), __float_as_uint(r1.w), __float_as_uint(r1.z), c + step,
-                          ordi, hi, thr);
+                          ordi, hi);
       nh_consider<STRICT>(b, dist2(xi, yi, r2.x, r2.y), __float_as_uint(r2.w), __float_as_uint(r2.z),
-                          c + 2 * step, ordi, hi, thr);
+                          c + 2 * step, ordi, hi);
       nh_consider<STRICT>(b, dist2(xi, yi, r3.x, r3.y), __float_as_uint(r3.w), __float_as_uint(r3.z),
-                          c + 3 * step, ordi, hi, thr);
+                          c + 3 * step, ordi, hi);
     }
     for (; c < q1; c += step) {
       const float4 r = rec[c];
-      nh_consider<STRICT>(b, dist2(xi, yi, r.x, r.y), __float_as_uint(r.w), __float_as_uint(r.z), c, ordi, hi, thr);
+      nh_consider<STRICT>(b, dist2(xi, yi, r.x, r.y), __float_as_uint(r.w), __float_as_uint(r.z), c, ordi, hi);
     }
   }
 }
@@ -1307,7 +1320,7 @@ __device__ __forceinline__ void nh_global_scan(const Geom& g, const Arena& a, in
     const int s0 = a.tile_start[t + W.x0], s1 = a.tile_start[t + W.x1 + 1];
     for (int c = s0 + sub; c < s1; c += step)
       nh_consider<STRICT>(b, dist2(xi, yi, a.xs[c], a.ys[c]), ord_f32(a.rho[c]), (unsigned)a.hs[c], -2 - c, ordi,
-                          hi, g.dm2);
+                          hi);
   }
 }
 
@@ -1347,8 +1360,8 @@ __device__ __forceinline__ void nh_staged(const Geom& g, const Arena& a, const R
       const Window W = query_window(g, g.win_r1, me.x, me.y);
       const int tx0 = W.x0 - R.rx0, tx1 = W.x1 - R.rx0, ty0 = W.y0 - R.ry0, ty1 = W.y1 - R.ry0;
       if (tx0 >= 0 && ty0 >= 0 && tx1 < R.rw && ty1 < R.rh) {
-        NhBest b{~0ull, -1};
-        nh_scan_staged<STRICT>(rec, L.ts, per_row, tx0, tx1, ty0, ty1, 0, 1, me.x, me.y, ordi, hi, g.r1sq, b);
+        NhBest b = nh_start(g.r1sq);
+        nh_scan_staged<STRICT>(rec, L.ts, per_row, tx0, tx1, ty0, ty1, 0, 1, me.x, me.y, ordi, hi, b);
         if (b.p >= 0) {
           b.p = slot_of(L, region_row_of(L, R.rh, b.p), b.p);
           decide_and_store(g, a, d, slot_of(L, row, p), (int)hi, ord_inv(ordi), b, ev_first);
@@ -1367,7 +1380,7 @@ __device__ __forceinline__ void nh_staged(const Geom& g, const Arena& a, const R
   for (int base = 0; base < nu; base += qpp) {  // uniform trip count
     const int qi = base + threadIdx.x / tpq;
     const bool active = qi < nu;
-    NhBest b{~0ull, -1};
+    NhBest b = nh_start(g.dm2);
     int slot = 0;
     unsigned hi = 0, ordi = 0;
     if (active) {
@@ -1380,7 +1393,7 @@ __device__ __forceinline__ void nh_staged(const Geom& g, const Arena& a, const R
       const Window W = query_window(g, g.win_dm, me.x, me.y);
       const int tx0 = W.x0 - R.rx0, tx1 = W.x1 - R.rx0, ty0 = W.y0 - R.ry0, ty1 = W.y1 - R.ry0;
       if (tx0 >= 0 && ty0 >= 0 && tx1 < R.rw && ty1 < R.rh) {
-        nh_scan_staged<STRICT>(rec, L.ts, per_row, tx0, tx1, ty0, ty1, sub, tpq, me.x, me.y, ordi, hi, g.dm2, b);
+        nh_scan_staged<STRICT>(rec, L.ts, per_row, tx0, tx1, ty0, ty1, sub, tpq, me.x, me.y, ordi, hi, b);
       } else {
         atomicOr(a.err, (uint32_t)E_WINDOW);
         nh_global_scan<STRICT>(g, a, ubase, W, sub, tpq, me.x, me.y, ordi, hi, b);
@@ -1408,7 +1421,7 @@ __device__ __forceinline__ void nh_global_region(const Geom& g, const Arena& a, 
   for (int base = 0; base < nq; base += qpp) {
     const int q = base + threadIdx.x / tpq;
     const bool active = q < nq;
-    NhBest b{~0ull, -1};
+    NhBest b = nh_start(g.dm2);
     int slot = 0;
     unsigned hi = 0;
     if (active) {
