@@ -4,7 +4,8 @@
 per-stage launches (plain form), ``run_batch`` clusters many events with
 persistent kernels replayed from a HIP graph (batched form). Inputs and
 outputs are torch tensors on the GPU; work is enqueued on the current torch
-stream. The serving loop lives in ``paper_2001_09761_amd.serve``.
+stream. ``Server`` (from ``paper_2001_09761_amd.serve``) is the online served
+form: events are submitted as they come and come back as futures.
 """
 from __future__ import annotations
 
@@ -16,7 +17,7 @@ from . import _lib
 from ._lib import (ClueError, KEEP_INTERMEDIATES, NO_FOLLOWERS, TIE_PAPER_STRICT, VALIDATE,  # noqa: F401
                    make_params)
 
-__all__ = ["Context", "ClueError", "VALIDATE", "KEEP_INTERMEDIATES", "TIE_PAPER_STRICT", "NO_FOLLOWERS",
+__all__ = ["Context", "Server", "ClueError", "VALIDATE", "KEEP_INTERMEDIATES", "TIE_PAPER_STRICT", "NO_FOLLOWERS",
            "footprint_bytes"]
 
 
@@ -246,3 +247,6 @@ class Context:
 
     def __exit__(self, *exc):
         self.close()
+
+
+from .serve import Server  # noqa: E402  (the served form builds on Context)

@@ -17,11 +17,17 @@ while new events keep arriving. Latency is completion minus arrival.
 The scheduling logic is backend-independent: ``GpuPoolBackend`` drives the
 HIP library on a device-resident event pool; tests also drive it with a CPU
 backend and a virtual clock.
+
+``Server`` is the online form of the same loop: callers ``submit`` events as
+they come and receive futures of their cluster ids.
 """
 from __future__ import annotations
 
 import gc
+import threading
 import time
+from collections import deque
+from concurrent.futures import Future
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -261,3 +267,238 @@ def make_pool(events, device):
     pool["is_seed"] = torch.empty(n, dtype=torch.uint8, device=device)
     pool["offsets"] = np.concatenate([[0], np.cumsum([e["x"].size for e in events])]).astype(np.int64)
     return pool
+
+
+def plan_batch(sizes, max_hits, max_events):
+    """How many events from the front of a FIFO form the next batch: as many
+    as fit ``max_hits`` hits and ``max_events`` events (each event alone
+    fits, so a non-empty queue always gives at least one)."""
+    k = hits = 0
+    for n in sizes:
+        if k >= max_events or hits + n > max_hits:
+            break
+        hits += n
+        k += 1
+    return k
+
+
+class _Slot:
+    def __init__(self, ctx, stream):
+        self.ctx = ctx
+        self.stream = stream
+
+
+class Server:
+    """Online served form: ``submit(x, y, layer, energy)`` queues one event and
+    returns a ``concurrent.futures.Future`` of its ``(cluster_id, is_seed)``
+    (int32 and uint8 device tensors, event-local as from ``Context.run``).
+
+    A worker thread takes queued events in arrival order and, whenever one of
+    the ``slots`` is free, gathers a batch of them (up to ``max_batch_hits``
+    hits and ``max_batch_events`` events) into one tensor per input and runs
+    the batched form on the slot's own stream; slots overlap on the GPU. Each
+    event's result is a view of its batch's output tensors. The device memory
+    the server works in is bounded when it is built (per slot: the context
+    arena plus one batch of inputs and outputs) and must fit ``hbm_budget``
+    bytes (0: no limit); events wait in the queue until a slot takes them.
+
+    Inputs may be torch tensors on the server's device or on the host, or
+    numpy arrays. Device inputs are read on the slot's stream after the work
+    that the caller's current stream had queued when ``submit`` was called.
+    An event with more than ``max_batch_hits`` hits fails its future with
+    ValueError. With the VALIDATE flag every batch is checked when it
+    completes and invalid input fails all futures of its batch; otherwise,
+    as with ``Context``, device-side errors are deferred, here to ``close()``.
+    Results are complete when their future resolves; they were allocated on
+    the slot's stream, so work that a caller queues on another stream before
+    dropping them should be covered by ``Tensor.record_stream``.
+    """
+
+    def __init__(self, dc, rho_c, delta_c, delta_o, *, max_batch_hits, max_batch_events=64, slots=2,
+                 hbm_budget=0, extent=None, bounds=None, n_layers=100, tuning=None, flags=0, kernel="flat",
+                 kernel_scale=0.0, device=None):
+        import torch
+
+        from . import Context, footprint_bytes
+        self._torch = torch
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else int(device))
+        self.max_batch_hits = int(max_batch_hits)
+        self.max_batch_events = int(max_batch_events)
+        per_slot = footprint_bytes(dc, rho_c, delta_c, delta_o, self.max_batch_hits, self.max_batch_events,
+                                   extent=extent, bounds=bounds, n_layers=n_layers, flags=flags, kernel=kernel,
+                                   kernel_scale=kernel_scale) + self.max_batch_hits * POOL_BYTES_PER_HIT
+        self.device_bytes = int(slots) * per_slot
+        if hbm_budget and self.device_bytes > hbm_budget:
+            raise ValueError(f"{slots} slots need {self.device_bytes} B of device memory, more than the "
+                             f"HBM budget of {hbm_budget} B")
+        from . import VALIDATE
+        self._validate = bool(flags & VALIDATE)
+        self._slots = []
+        try:
+            for _ in range(int(slots)):
+                ctx = Context(dc, rho_c, delta_c, delta_o, max_hits=self.max_batch_hits,
+                              max_events=self.max_batch_events, extent=extent, bounds=bounds, n_layers=n_layers,
+                              flags=flags, device=self.device.index, kernel=kernel, kernel_scale=kernel_scale)
+                if tuning:
+                    ctx.set_tuning(**tuning)
+                sl = _Slot(ctx, torch.cuda.Stream(device=self.device))  # default priority
+                self._slots.append(sl)
+                # one full batch of inputs and outputs, allocated and released on
+                # the slot's stream, leaves its blocks in torch's cache for the
+                # batches to come (the first batches then allocate nothing new)
+                with torch.cuda.stream(sl.stream):
+                    m = self.max_batch_hits
+                    warm = [torch.empty(m, dtype=dt, device=self.device)
+                            for dt in (torch.float32,) * 3 + (torch.int32,) * 3 + (torch.uint8,)]
+                    del warm
+        except Exception:
+            for sl in self._slots:
+                sl.ctx.close()
+            raise
+        self._cv = threading.Condition()
+        self._queue = deque()  # (n, inputs, ready event, future)
+        self._closing = False
+        self._thread = threading.Thread(target=self._serve, name="clue-server", daemon=True)
+        self._thread.start()
+
+    def _as_tensor(self, v, dtype, name, n):
+        torch = self._torch
+        t = v if isinstance(v, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(v))
+        if t.dtype != dtype or t.dim() != 1 or t.numel() != n:
+            raise TypeError(f"{name} must be a 1-D {dtype} array of {n} elements")
+        if t.device.type != "cpu" and t.device != self.device:
+            raise TypeError(f"{name} is on {t.device}, the server runs on {self.device}")
+        return t
+
+    def submit(self, x, y, layer, energy):
+        """Queue one event; returns a Future of (cluster_id, is_seed)."""
+        torch = self._torch
+        fut = Future()
+        n = int(x.numel()) if isinstance(x, torch.Tensor) else int(np.asarray(x).size)
+        ins = (self._as_tensor(x, torch.float32, "x", n), self._as_tensor(y, torch.float32, "y", n),
+               self._as_tensor(layer, torch.int32, "layer", n), self._as_tensor(energy, torch.float32, "energy", n))
+        if n > self.max_batch_hits:
+            fut.set_exception(ValueError(f"event of {n} hits exceeds max_batch_hits = {self.max_batch_hits}"))
+            return fut
+        ready = None
+        if any(t.device.type != "cpu" for t in ins):
+            ready = torch.cuda.Event()
+            ready.record(torch.cuda.current_stream(self.device))
+        with self._cv:
+            if self._closing:
+                raise RuntimeError("server is closed")
+            self._queue.append((n, ins, ready, fut))
+            self._cv.notify()
+        return fut
+
+    def _launch(self, slot, items):
+        torch = self._torch
+        sl = self._slots[slot]
+        dev = self.device
+        k = len(items)
+        with torch.cuda.stream(sl.stream):
+            for _, _, ready, _ in items:
+                if ready is not None:
+                    sl.stream.wait_event(ready)
+            # one batch tensor per input column (a few launches per batch, not per event)
+            cols = list(zip(*[[t.to(dev, non_blocking=True) for t in it[1]] for it in items]))
+            x, y, layer, energy = (torch.cat(c) if k > 1 else c[0] for c in cols)
+            sizes = [it[0] for it in items]
+            total = int(sum(sizes))
+            counts = torch.tensor(sizes, dtype=torch.int64).pin_memory().to(dev, non_blocking=True)
+            event = torch.repeat_interleave(torch.arange(k, dtype=torch.int32, device=dev), counts,
+                                            output_size=total)
+            cid = torch.empty(total, dtype=torch.int32, device=dev)
+            seed = torch.empty(total, dtype=torch.uint8, device=dev)
+            sl.ctx.run_batch(event, k, x, y, layer, energy, cid, seed, stream=sl.stream)
+            done = torch.cuda.Event()
+            done.record(sl.stream)
+        # each event's result is a view of the batch outputs
+        outs, a = [], 0
+        for n, _, _, fut in items:
+            outs.append((fut, cid[a:a + n], seed[a:a + n]))
+            a += n
+        return done, outs, (items, x, y, layer, energy, event)
+
+    def _finish(self, slot, outs, err=None):
+        if err is None and self._validate:
+            try:
+                self._slots[slot].ctx.status(self._slots[slot].stream)
+            except Exception as e:  # invalid input fails the whole batch
+                err = e
+        for fut, cid, seed in outs:
+            if err is None:
+                fut.set_result((cid, seed))
+            else:
+                fut.set_exception(err)
+
+    def _serve(self):
+        busy = {}  # slot -> (completion event, outputs, inputs held until done)
+        try:
+            self._loop(busy)
+        except BaseException as e:  # the worker cannot go on: fail what it holds
+            with self._cv:
+                self._closing = True
+                pending = [q[3] for q in self._queue]
+                self._queue.clear()
+            for _, outs, _ in busy.values():
+                pending += [o[0] for o in outs]
+            for fut in pending:
+                if not fut.done():
+                    fut.set_exception(RuntimeError(f"server worker stopped: {e!r}"))
+
+    def _loop(self, busy):
+        torch = self._torch
+        torch.cuda.set_device(self.device)
+        free = list(range(len(self._slots)))
+        while True:
+            launches = []
+            with self._cv:
+                while not self._queue and not busy and not self._closing:
+                    self._cv.wait()
+                if self._closing and not self._queue and not busy:
+                    return
+                while free and self._queue:
+                    sizes = [q[0] for q in list(self._queue)[: self.max_batch_events]]
+                    k = plan_batch(sizes, self.max_batch_hits, self.max_batch_events)
+                    launches.append((free.pop(0), [self._queue.popleft() for _ in range(k)]))
+            for slot, items in launches:
+                try:
+                    busy[slot] = self._launch(slot, items)
+                except Exception as e:  # argument or launch error: fail this batch, keep serving
+                    self._finish(slot, [(it[3], None, None) for it in items], err=e)
+                    free.append(slot)
+            progressed = False
+            for slot in list(busy):
+                done, outs, _ = busy[slot]
+                if done.query():
+                    del busy[slot]
+                    self._finish(slot, outs)
+                    free.append(slot)
+                    progressed = True
+            if busy and not progressed:
+                time.sleep(2e-5)
+
+    def close(self):
+        """Serves every queued event, stops the worker and frees the slots;
+        then raises a deferred device-side error of any slot, if there was one."""
+        with self._cv:
+            self._closing = True
+            self._cv.notify()
+        self._thread.join()
+        err = None
+        for sl in self._slots:
+            try:
+                sl.ctx.status(sl.stream)
+            except Exception as e:
+                err = err or e
+            sl.ctx.close()
+        self._slots = []
+        if err is not None:
+            raise err
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

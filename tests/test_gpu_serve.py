@@ -105,3 +105,42 @@ def test_autotuner_keeps_outputs_identical(tmp_path):
         key = autotune.cache_key(p, b["x"].size, 4)
         autotune.store_cached(key, best, str(tmp_path / "t.json"))
         assert autotune.load_cached(key, str(tmp_path / "t.json"))["tile_size"] == best["tile_size"]
+
+
+def test_online_server_futures_equal_run():
+    """Server.submit from host arrays and from device tensors: every future
+    holds the event's result as Context.run gives it alone; batches form over
+    two slots; an event above max_batch_hits fails its own future only."""
+    import torch
+    import paper_2001_09761_amd as clue
+    dev = torch.device("cuda", 0)
+    evs = _events(24, n_layers=6, seed=13)
+    p = _params(6)
+    cap = 4 * max(e["x"].size for e in evs)
+    srv = clue.Server(p["dc"], p["rho_c"], p["delta_c"], p["delta_o"], max_batch_hits=cap, max_batch_events=8,
+                      slots=2, extent=200.0, n_layers=6)
+    futs = []
+    with srv:
+        for i, ev in enumerate(evs):
+            if i % 2:
+                t = to_dev(ev, dev)
+                futs.append(srv.submit(t["x"], t["y"], t["layer"], t["energy"]))
+            else:
+                futs.append(srv.submit(ev["x"], ev["y"], ev["layer"], ev["energy"]))
+        big = np.zeros(cap + 1, np.float32)
+        f_big = srv.submit(big, big, np.zeros(cap + 1, np.int32), big)
+        results = [f.result(timeout=60) for f in futs]
+    with pytest.raises(ValueError):
+        f_big.result(timeout=1)
+    with pytest.raises(RuntimeError):
+        srv.submit(evs[0]["x"], evs[0]["y"], evs[0]["layer"], evs[0]["energy"])
+    with clue.Context(p["dc"], p["rho_c"], p["delta_c"], p["delta_o"], max_hits=max(e["x"].size for e in evs),
+                      extent=200.0, n_layers=6) as ctx:
+        for i, (ev, (cid, seed)) in enumerate(zip(evs, results)):
+            t = to_dev(ev, dev)
+            rc, rs = ctx.run(t["x"], t["y"], t["layer"], t["energy"])
+            assert torch.equal(cid, rc) and torch.equal(seed, rs), f"event {i}"
+            if i % 6 == 0:
+                ref = oracle.run_event(ev, p, n_threads=NT, want=())
+                assert np.array_equal(cid.cpu().numpy(), ref["cluster_id"])
+        ctx.status()

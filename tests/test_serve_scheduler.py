@@ -129,3 +129,19 @@ def test_summary_fields():
                                                                         [e["x"].size for e in evs])
     s = st.summary()
     assert s["events"] == 5 and s["p99_ms"] >= s["p50_ms"] > 0 and s["hits"] == sum(e["x"].size for e in evs)
+
+
+def test_plan_batch_takes_the_longest_fitting_prefix():
+    from paper_2001_09761_amd.serve import plan_batch
+    assert plan_batch([], 100, 4) == 0
+    assert plan_batch([10], 10, 1) == 1
+    assert plan_batch([5, 5, 5], 12, 10) == 2          # hit capacity
+    assert plan_batch([5, 5, 5], 100, 2) == 2          # event capacity
+    assert plan_batch([3, 9, 1], 10, 10) == 1          # FIFO: no reordering past a large event
+    rng = np.random.default_rng(3)
+    for _ in range(200):
+        sizes = list(rng.integers(1, 50, rng.integers(1, 20)))
+        cap_h, cap_e = int(rng.integers(50, 200)), int(rng.integers(1, 10))
+        k = plan_batch(sizes, cap_h, cap_e)
+        assert 1 <= k <= min(cap_e, len(sizes)) and sum(sizes[:k]) <= cap_h
+        assert k == min(cap_e, len(sizes)) or sum(sizes[:k + 1]) > cap_h
