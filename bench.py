@@ -77,6 +77,15 @@ def cpu_baseline(events, params, budget_s=12.0):
                       f"{threads} threads over (event, layer) units, {dt:.2f} s wall"}
 
 
+def tuning_kwargs(t):
+    """A tuner result as Context.set_tuning keyword arguments."""
+    kw = {k: v for k, v in t.items() if k in ("tile_size", "threads_per_query", "lds_cap", "nh_first_radius",
+                                                 "density_quads", "expansion")}
+    if "block" in t:
+        kw["block_x"], kw["block_y"] = t["block"]
+    return kw
+
+
 def apply_tuning(ctx, batch, n_events, params, log):
     """Tuning from the package's MI355X cache, else from an autotuner run."""
     from paper_2001_09761_amd import autotune
@@ -234,10 +243,7 @@ def main():
             with clue.Context(params["dc"], params["rho_c"], params["delta_c"], params["delta_o"], max_hits=n,
                               max_events=args.events, extent=params["extent"], n_layers=params["n_layers"],
                               kernel=kname, kernel_scale=ks) as kctx:
-                kctx.set_tuning(tile_size=tuning["tile_size"], threads_per_query=tuning["threads_per_query"],
-                                block_x=tuning["block"][0], block_y=tuning["block"][1], lds_cap=tuning["lds_cap"],
-                                nh_first_radius=tuning["nh_first_radius"], density_quads=tuning["density_quads"],
-                                expansion=tuning.get("expansion", 1))
+                kctx.set_tuning(**tuning_kwargs(tuning))
                 krun = lambda: kctx.run_batch(d["event"], args.events, d["x"], d["y"], d["layer"], d["energy"],  # noqa: E731
                                               cid, seed)
                 wall_k, _ = timed(krun, max(3, args.steps // 4), 2)
@@ -555,9 +561,7 @@ def extras(args, params, log):
     n_hits = [e["x"].size for e in pool_events]
     cap = 8 * max(n_hits)
     be = GpuPoolBackend(params, pool, slots=2, max_batch_hits=cap, max_batch_events=8,
-                        tuning={k: v for k, v in dict(tuning).items() if k in ("tile_size", "threads_per_query",
-                                                                             "lds_cap", "nh_first_radius",
-                                                                             "density_quads")})
+                        tuning=tuning_kwargs(tuning))
     def served(rate):
         arrivals = gen.poisson_arrivals(rate, len(pool_events))
         sch = Scheduler(be, hbm_budget_bytes=64 << 30, max_batch_hits=cap, max_batch_events=8)
@@ -581,8 +585,7 @@ def extras(args, params, log):
 
     # online form: the same events submitted as device tensors in one burst;
     # each future's latency runs from its submit to its completion callback
-    srv_tuning = {k: v for k, v in dict(tuning).items()
-                  if k in ("tile_size", "threads_per_query", "lds_cap", "nh_first_radius", "density_quads")}
+    srv_tuning = tuning_kwargs(tuning)
     with clue.Server(params["dc"], params["rho_c"], params["delta_c"], params["delta_o"], max_batch_hits=cap,
                      max_batch_events=8, slots=2, extent=200.0, n_layers=100, tuning=srv_tuning) as srv:
         offs_p = pool["offsets"]
@@ -603,14 +606,36 @@ def extras(args, params, log):
         for f in futs:
             f.result()
         wall = time.perf_counter() - t0
-    lat_ms = sorted(x * 1e3 for x in lat)
+        # the same burst from pinned host memory: the copies in run on the slots'
+        # streams, overlapped with the other slot's kernels (PCIe-inclusive)
+        host_views = [tuple(t.cpu().pin_memory() for t in v) for v in views]
+        for f in [srv.submit(*v) for v in host_views]:
+            f.result()
+        torch.cuda.synchronize()
+        lat_h = [0.0] * len(views)
+        t0 = time.perf_counter()
+        futs = []
+        for i, v in enumerate(host_views):
+            ts = time.perf_counter()
+            f = srv.submit(*v)
+            f.add_done_callback(lambda _f, i=i, ts=ts: lat_h.__setitem__(i, time.perf_counter() - ts))
+            futs.append(f)
+        for f in futs:
+            f.result()
+        wall_h = time.perf_counter() - t0
     hits = int(sum(v[0].numel() for v in views))
-    res["online_server"] = {"workload": f"{len(views)} events of 100 layers x U[1000,10000] hits submitted in one "
-                                        f"burst as device tensors", "slots": 2, "max_batch_events": 8,
-                            "events_per_s": round(len(views) / wall, 1), "hits_per_s": round(hits / wall, 1),
-                            "p50_ms": round(lat_ms[len(lat_ms) // 2], 4),
-                            "p99_ms": round(lat_ms[min(len(lat_ms) - 1, int(0.99 * len(lat_ms)))], 4)}
-    log(f"online server: {res['online_server']['events_per_s']} events/s")
+
+    def _row(latencies, wall_s, src):
+        ms = sorted(x * 1e3 for x in latencies)
+        return {"workload": f"{len(views)} events of 100 layers x U[1000,10000] hits submitted in one burst "
+                            f"as {src}", "slots": 2, "max_batch_events": 8,
+                "events_per_s": round(len(views) / wall_s, 1), "hits_per_s": round(hits / wall_s, 1),
+                "p50_ms": round(ms[len(ms) // 2], 4), "p99_ms": round(ms[min(len(ms) - 1, int(0.99 * len(ms)))], 4)}
+
+    res["online_server"] = _row(lat, wall, "device tensors")
+    res["online_server_pinned_host"] = _row(lat_h, wall_h, "pinned host tensors (PCIe-inclusive)")
+    log(f"online server: {res['online_server']['events_per_s']} events/s from device, "
+        f"{res['online_server_pinned_host']['events_per_s']} from pinned host")
     return res
 
 
