@@ -72,3 +72,15 @@ def test_oracle_and_product_share_nothing():
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 src = open(os.path.join(dirpath, f)).read()
                 assert "clue_oracle" not in src and "import oracle" not in src and "from oracle" not in src, f
+
+
+def test_c_consumer_links_and_rejects_bad_usage():
+    """The plain C consumer of the ABI links against libclue.so and the HIP
+    runtime; run without arguments it prints its usage and fails before any
+    HIP call (no GPU needed)."""
+    import subprocess
+    exe = os.path.join(os.path.dirname(os.path.abspath(__file__)), "c_abi", "clue_c_consumer")
+    if not os.path.exists(exe):
+        pytest.skip("C consumer not built (__graft_entry__.build)")
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 1 and "usage" in r.stderr
