@@ -280,6 +280,7 @@ static void compute_cfg(clue_ctx* c) {
   const int lds = lds_bytes_for(c->g);
   // a multiple of kQueues: streaming kernels give each XCD one run of chunks
   c->cfg.persist_blocks_stream = (c->n_cu * std::min(occupancy_blocks_per_cu(0, 0), 8) + kQueues - 1) / kQueues * kQueues;
+  c->cfg.persist_blocks_scatter = (c->n_cu * kScatterBlocksPerCU + kQueues - 1) / kQueues * kQueues;
   c->cfg.persist_blocks_rho = c->n_cu * occupancy_blocks_per_cu(1, lds);
   c->cfg.persist_blocks_nh = c->n_cu * occupancy_blocks_per_cu(3, lds_bytes_nh(c->g));
   if (std::getenv("CLUE_VERBOSE"))

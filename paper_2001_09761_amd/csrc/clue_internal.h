@@ -19,6 +19,7 @@ constexpr int kMaxLdsCap = 2048;
 __host__ __device__ constexpr int lds_records_density(int lds_cap) { return (lds_cap * (16 + 2 + 8) + 15) & ~15; }
 constexpr int kStagePer = 4;       // staged hits per lane per round (loads in flight)
 constexpr int kPlaceU = 4;         // hits per lane per step of the label kernels
+constexpr int kScatterBlocksPerCU = 2;  // persistent k_scatter workgroups per CU
 
 // Counters in device memory, cleared at the start of every run. Each sits on
 // its own 256-byte line so that atomics on different counters do not
@@ -139,6 +140,8 @@ extern const char* const kStageNames[S_COUNT];
 struct LaunchCfg {
   bool graph_mode;   // persistent kernels reading the descriptor from device memory
   int persist_blocks_stream;  // persistent grid of the streaming kernels
+  int persist_blocks_scatter; // persistent grid of k_scatter (fewer workgroups: its
+                              // scattered writes complete lines in L2 more often)
   int persist_blocks_rho;     // persistent grid of the density kernel
   int persist_blocks_nh;      // persistent grid of the nearest-higher kernel
   int persist_blocks_scan;    // persistent grid of the scans

@@ -1797,7 +1797,7 @@ static hipError_t launch_all(const Geom& g, const Arena& a, DescArg<G> dg, const
   mark();
   k_scan<G, SCAN_TILES><<<g_scan_t, kWG, 0, s>>>(dg, g, a);
   mark();
-  k_scatter<G><<<stream_grid(cdiv(n, kPlaceU)), kWG, 0, s>>>(dg, g, a);
+  k_scatter<G><<<G ? cfg.persist_blocks_scatter : stream_grid(cdiv(n, kPlaceU)), kWG, 0, s>>>(dg, g, a);
   mark();
   k_place<G><<<stream_grid(n), kWG, 0, s>>>(dg, g, a);
   mark();
