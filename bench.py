@@ -72,9 +72,22 @@ def cpu_baseline(events, params, budget_s=12.0):
         if time.perf_counter() - t0 > budget_s:
             break
     dt = time.perf_counter() - t0
+    # the paper's baseline column: one thread, on the first event
+    t1 = time.perf_counter()
+    oracle.run_event(events[0], params, n_threads=1, want=())
+    dt1 = time.perf_counter() - t1
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": hits / dt, "unit": "hits/s", "cores": threads, "kind": "oracle",
             "sample": f"{done} of the workload's 1M-hit events ({hits} hits), oracle grid form, "
-                      f"{threads} threads over (event, layer) units, {dt:.2f} s wall"}
+                      f"{threads} threads over (event, layer) units, {dt:.2f} s wall",
+            "single_thread": {"value": events[0]["x"].size / dt1, "unit": "hits/s",
+                              "sample": f"the first 1M-hit event on 1 thread, {dt1:.2f} s wall"},
+            "cpu_model": model}
 
 
 def tuning_kwargs(t):
@@ -192,6 +205,31 @@ def main():
     ms_per_step = wall_b / args.steps * 1e3
     value = n * args.steps / wall_b
 
+    # ---- per-step times (HIP events around each step), median and p99 -------
+    step_ms = []
+    for _ in range(max(20, args.steps)):
+        s0 = torch.cuda.Event(enable_timing=True)
+        s1 = torch.cuda.Event(enable_timing=True)
+        s0.record(stream)
+        step_batched()
+        s1.record(stream)
+        s1.synchronize()
+        step_ms.append(s0.elapsed_time(s1))
+
+    # ---- achievable copy bandwidth on this GPU: 1 GiB read + 1 GiB written --
+    ca = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+    cb = torch.empty_like(ca)
+    torch.neg(ca, out=cb)
+    c0 = torch.cuda.Event(enable_timing=True)
+    c1 = torch.cuda.Event(enable_timing=True)
+    c0.record(stream)
+    for _ in range(5):
+        torch.neg(ca, out=cb)
+    c1.record(stream)
+    c1.synchronize()
+    copy_gbps = 5 * 2 * ca.numel() * 4 / (c0.elapsed_time(c1) / 1e3) / 1e9
+    del ca, cb
+
     # ---- plain per-event launches on the same events -----------------------
     psteps = max(2, args.steps // 4)
     wall_p, _ = timed(step_plain, psteps, 1)
@@ -226,11 +264,20 @@ def main():
     dom_ms = stages[dom]
     achieved = ALG_BYTES[dom] * n / (dom_ms / 1e3) / 1e9
     traffic = None
+    pipeline_traffic = None
     try:
         prof = json.load(open(PROFILE_TRAFFIC))
         if prof.get("kernel_source_sha") == kernel_source_sha() and prof.get("stage") == dom \
                 and int(prof.get("hits_per_launch", -1)) == n:
             traffic = prof["hbm_bytes_per_launch"]
+            per_stage = prof.get("per_stage_hbm_bytes_per_launch") or {}
+            if per_stage and set(per_stage) >= set(stages):
+                b_hit = sum(per_stage.values()) / n
+                pipeline_traffic = {"measured_bytes_per_hit": round(b_hit, 2),
+                                    "measured_GBps": round(b_hit * value / 1e9, 1),
+                                    "measured_frac_of_peak": round(b_hit * value / 1e9 / HBM_PEAK_GBPS, 4),
+                                    "amplification_vs_algorithmic": round(b_hit / PIPELINE_ALG_BYTES, 3),
+                                    "source": os.path.relpath(PROFILE_TRAFFIC, ROOT)}
     except (OSError, ValueError, KeyError):
         traffic = None
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
@@ -288,11 +335,15 @@ def main():
         "batched_over_plain": round(value / plain_value, 3),
         "plain_equals_batched": plain_ok,
         "device_time_per_step_ms": round(dev_b / args.steps * 1e3, 4),
+        "step_ms_p50": percentile(step_ms, 50), "step_ms_p99": percentile(step_ms, 99),
+        "hbm_copy_GBps": round(copy_gbps, 1),
         "pipeline_alg_GBps": round(PIPELINE_ALG_BYTES * value / 1e9, 1),
         "pipeline_alg_frac_of_hbm_peak": round(PIPELINE_ALG_BYTES * value / 1e9 / HBM_PEAK_GBPS, 4),
         "event_latency_ms": {"plain_1M_p50": percentile(lat_plain, 50), "plain_1M_p99": percentile(lat_plain, 99)},
         "stages_ms": {k: round(v, 4) for k, v in stages.items()},
         "roofline": roofline,
+        "pipeline_traffic": pipeline_traffic,
+        "input_hashes": [gen.event_hash(ev)[:12] for ev in events],
         "input_generation_s": round(t_gen, 2),
     }
     if kernels:
@@ -310,8 +361,10 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-STAGE_KERNEL = {"grid_hist": "k_hist<true", "grid_scatter": "k_scatter<true", "density": "k_density<true",
-                "nearest_higher": "k_nearest_higher<true", "labels": "k_label<true"}
+STAGE_KERNEL = {"clear": "k_clear<true", "grid_hist": "k_hist<true", "grid_scan": "k_scan<true, 0>",
+                "grid_scatter": "k_scatter<true", "grid_place": "k_place<true", "density": "k_density<true",
+                "nearest_higher": "k_nearest_higher<true", "seed_scan": "k_scan<true, 2>", "labels": "k_label<true",
+                "follower_lists": "k_follow_sort<true"}
 
 
 def _pmc_rows(d):
@@ -350,11 +403,22 @@ def traffic_summary(d, stage, n_events):
     sf, sw = gib / (f_c * 1024.0), gib / (w_c * 1024.0)
     hbm = f_k * 1024.0 * sf + w_k * 1024.0 * sw
     hits = 10000 * 100 * n_events
+    # every stage's batched kernel, for the whole-pipeline measured traffic
+    fetch_rows, write_rows = _pmc_rows(os.path.join(d, "fetch")), _pmc_rows(os.path.join(d, "write"))
+    per_stage = {}
+    for st, km in STAGE_KERNEL.items():
+        try:
+            fs_k, _ = _mean_counter(fetch_rows, "FETCH_SIZE", km)
+            ws_k, _ = _mean_counter(write_rows, "WRITE_SIZE", km)
+        except SystemExit:
+            continue
+        per_stage[st] = fs_k * 1024.0 * sf + ws_k * 1024.0 * sw
     out = {"stage": stage, "kernel_match": kname, "kernel_source_sha": kernel_source_sha(),
            "hits_per_launch": hits, "fetch_kib_per_dispatch": f_k, "write_kib_per_dispatch": w_k,
            "dispatches": [nf, nw], "copy_fetch_kib": f_c, "copy_write_kib": w_c,
            "scale_fetch": sf, "scale_write": sw, "hbm_bytes_per_launch": hbm,
-           "hbm_bytes_per_hit": hbm / hits, "alg_bytes_per_hit": ALG_BYTES[stage]}
+           "hbm_bytes_per_hit": hbm / hits, "alg_bytes_per_hit": ALG_BYTES[stage],
+           "per_stage_hbm_bytes_per_launch": per_stage}
     with open(PROFILE_TRAFFIC, "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps(out))
