@@ -110,3 +110,18 @@ def test_delta_o_sweep_fig4(expansion):
         noise.append(int((cid < 0).sum()))
         prev = got
     assert noise[0] > noise[1] > noise[2] > noise[3] >= noise[4], noise
+
+
+def test_dfs_paper_strict_and_batches():
+    """The k-way walk under the paper's strict ties (equal densities never
+    higher) and over a batch whose events share no numbering."""
+    import paper_2001_09761_amd as clue
+    ev = adversarial_event(12, n=900, n_layers=3, unit_weights=True)
+    p = dict(dc=2.0, rho_c=5.0, delta_c=2.0, delta_o=4.0, bounds=(0, 0, 20, 20), n_layers=3)
+    for batched in (False, True):
+        got = gpu_run(ev, p, batched=batched, tuning=DFS, flags=clue.KEEP_INTERMEDIATES | clue.TIE_PAPER_STRICT)
+        assert_parity(got, _ref(ev, p, paper_strict=True), where=f"strict dfs batched={batched}")
+    evs = [adversarial_event(40 + e, n=300 + 40 * e, n_layers=3) for e in range(5)]
+    b = gen.concat_events(evs)
+    got = gpu_run(b, p, batched=True, n_events=b["n_events"], tuning=DFS)
+    assert_parity(got, _ref(b, p), where="adversarial batch dfs")
