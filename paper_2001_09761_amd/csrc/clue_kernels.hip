@@ -1154,8 +1154,14 @@ __device__ __forceinline__ void density_global_region(const Geom& g, const Arena
   }
 }
 
+// The flat-kernel quad path is built for seven waves per SIMD (72 VGPRs), so
+// that an LDS cap of up to 768 staged hits fits seven workgroups per CU; the
+// compiler then keeps one item-level value in scratch, reloaded once per work
+// item. The other instances keep their registers (they would spill in loops).
+constexpr int density_min_waves(int maxl, int k) { return maxl == 2 && k == 0 ? 7 : 1; }
+
 template <bool G, int MAXL, int K>
-__global__ __launch_bounds__(kWG) void k_density(DescArg<G> dg, Geom g, Arena a) {
+__global__ __launch_bounds__(kWG, density_min_waves(MAXL, K)) void k_density(DescArg<G> dg, Geom g, Arena a) {
   const RunDesc d = dg.get();
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int s_rows[kRowMetaInts];

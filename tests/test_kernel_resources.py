@@ -2,10 +2,11 @@
 
 A spill turns into per-lane scratch memory traffic on every loop trip of the
 tile-block kernels, so the compiler's resource report (built here on the CPU)
-must show zero scratch for every kernel but one. The nearest-higher kernel is
-built for eight waves per SIMD (64 VGPRs), and the compiler then keeps one
-8-byte value in scratch: stored once per workgroup and reloaded once per work
-item, outside the candidate loops. That kernel may use up to 16 bytes."""
+must show zero scratch for every kernel but two. The nearest-higher and
+density kernels are built for eight and seven waves per SIMD (64 and 72
+VGPRs), and the compiler then keeps one 8-byte value in scratch: stored once
+per workgroup and reloaded once per work item, outside the candidate loops.
+Those kernels may use up to 16 bytes."""
 import os
 import re
 import shutil
@@ -38,5 +39,6 @@ def test_no_scratch_spills(tmp_path):
             report[name] = int(m.group(1))
     kernels = {k: v for k, v in report.items() if "k_" in k}
     assert len(kernels) >= 20, sorted(report)
-    spills = {k: v for k, v in kernels.items() if v and not ("k_nearest_higher" in k and v <= 16)}
+    spills = {k: v for k, v in kernels.items()
+              if v and not (("k_nearest_higher" in k or "k_density" in k) and v <= 16)}
     assert not spills, spills
