@@ -93,7 +93,7 @@ def cpu_baseline(events, params, budget_s=12.0):
 def tuning_kwargs(t):
     """A tuner result as Context.set_tuning keyword arguments."""
     kw = {k: v for k, v in t.items() if k in ("tile_size", "threads_per_query", "lds_cap", "nh_first_radius",
-                                                 "density_quads", "expansion")}
+                                                 "density_quads", "expansion", "plain_lds_cap")}
     if "block" in t:
         kw["block_x"], kw["block_y"] = t["block"]
     return kw

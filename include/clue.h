@@ -205,6 +205,9 @@ typedef struct {
                                hit; 2: each hit merges its own window lists;
                                3: as 1, one lane merging each quad in order;
                                <= 0 keep */
+  int32_t plain_lds_cap;    /* LDS cap of the plain form (clue_run, one event per
+                               launch, fewer work items in flight); <= 0 keep
+                               (initially the same as lds_cap) */
   int32_t expansion;        /* cluster-id propagation (Sec. 2.2, Algorithm 3):
                                1: every hit follows nearest-higher links to its
                                root (pointer jumping, n-way); 2: one thread per

@@ -206,10 +206,10 @@ class Context:
         self.max_events = max(self.max_events, me)
 
     def set_tuning(self, tile_size=0.0, threads_per_query=0, block_x=0, block_y=0, lds_cap=0,
-                   nh_first_radius=-1.0, density_quads=0, expansion=0):
+                   nh_first_radius=-1.0, density_quads=0, expansion=0, plain_lds_cap=0):
         """Change the kernel tuning (results are identical for every tuning)."""
         t = _lib.ClueTuning(float(tile_size), int(threads_per_query), int(block_x), int(block_y), int(lds_cap),
-                            float(nh_first_radius), int(density_quads), int(expansion))
+                            float(nh_first_radius), int(density_quads), int(plain_lds_cap), int(expansion))
         self._check(self._L.clue_set_tuning(self._ctx, ctypes.byref(t)))
 
     def tuning(self):
@@ -218,7 +218,8 @@ class Context:
         self._check(self._L.clue_get_tuning(self._ctx, ctypes.byref(t), ctypes.byref(h)))
         return dict(tile_size=t.tile_size, threads_per_query=t.threads_per_query, block_x=t.block_x,
                     block_y=t.block_y, lds_cap=t.lds_cap, nh_first_radius=t.nh_first_radius,
-                    density_quads=t.density_quads, expansion=t.expansion, halo=h.value)
+                    density_quads=t.density_quads, plain_lds_cap=t.plain_lds_cap, expansion=t.expansion,
+                    halo=h.value)
 
     def enable_stage_timing(self, on=True):
         self._check(self._L.clue_enable_stage_timing(self._ctx, 1 if on else 0))

@@ -40,7 +40,7 @@ class ClueTuning(ctypes.Structure):
         ("tile_size", ctypes.c_float), ("threads_per_query", ctypes.c_int32),
         ("block_x", ctypes.c_int32), ("block_y", ctypes.c_int32),
         ("lds_cap", ctypes.c_int32), ("nh_first_radius", ctypes.c_float),
-        ("density_quads", ctypes.c_int32), ("expansion", ctypes.c_int32),
+        ("density_quads", ctypes.c_int32), ("plain_lds_cap", ctypes.c_int32), ("expansion", ctypes.c_int32),
     ]
 
 

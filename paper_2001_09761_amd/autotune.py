@@ -97,7 +97,7 @@ def _apply(ctx, t):
     bx, by = t["block"]
     ctx.set_tuning(tile_size=t["tile_size"], threads_per_query=t["threads_per_query"], block_x=bx, block_y=by,
                    lds_cap=t["lds_cap"], nh_first_radius=t["nh_first_radius"], density_quads=t["density_quads"],
-                   expansion=t.get("expansion", 1))
+                   expansion=t.get("expansion", 1), plain_lds_cap=t.get("plain_lds_cap", 0))
 
 
 def autotune(ctx, batch, n_events, params, *, reps=3, space=None, stage_times=False, log=print, sweeps=2,

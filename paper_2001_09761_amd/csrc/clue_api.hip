@@ -24,6 +24,8 @@ struct clue_ctx {
   int n_cu = 1;
   float tile = 0.0f;
   int tpq = 1, bx = 8, by = 8, lds_cap = kDefaultLdsCap;
+  int plain_cap = 0;  // LDS cap of the plain form (clue_run); 0: lds_cap
+  Geom g_plain{};     // g with the plain form's LDS cap
   float r1 = -1.0f;  // nearest-higher first radius; negative: default d_m / 4
   int quads = 1;      // density strategy (1 quads by search, 2 per-query merge, 3 quads by merge)
   int expansion = 1;  // labels: 1 pointer jumping, 2 depth-first walk per seed
@@ -466,6 +468,9 @@ static int run_common(clue_ctx* c, int64_t n, int32_t n_events, int32_t event_ba
   HIP_TRY(c, hipSetDevice(c->device));
   hipStream_t s = (hipStream_t)stream;
   RunDesc d{};
+  // the plain form may stage a different number of hits per work item
+  c->g_plain = c->g;
+  if (c->plain_cap > 0) c->g_plain.lds_cap = c->plain_cap;
   d.n = (int32_t)n;
   d.n_events = n_events;
   d.x = x;
@@ -484,7 +489,7 @@ static int run_common(clue_ctx* c, int64_t n, int32_t n_events, int32_t event_ba
   if (!batched) {
     LaunchCfg cfg = c->cfg;
     cfg.graph_mode = false;
-    HIP_TRY(c, launch_pipeline(c->g, c->a, d, cfg, s, ev));
+    HIP_TRY(c, launch_pipeline(c->g_plain, c->a, d, cfg, s, ev));
   } else {
     HIP_TRY(c, launch_set_desc(d, c->a.desc, s));
     if (ev) {
@@ -716,6 +721,9 @@ int clue_set_tuning(clue_ctx* c, const clue_tuning* t) {
   const int tpq = t->threads_per_query > 0 ? t->threads_per_query : c->tpq;
   const int bx = t->block_x > 0 ? t->block_x : c->bx, by = t->block_y > 0 ? t->block_y : c->by;
   const int cap = t->lds_cap > 0 ? t->lds_cap : c->lds_cap;
+  const int plain_cap = t->plain_lds_cap > 0 ? t->plain_lds_cap : c->plain_cap;
+  if (plain_cap != 0 && (plain_cap < 64 || plain_cap > kMaxLdsCap))
+    return set_err(c, CLUE_ERR_ARG, "plain_lds_cap must be within 64..2048 hits");
   const float r1 = t->nh_first_radius >= 0.0f ? t->nh_first_radius : c->r1;
   const int quads = t->density_quads > 0 ? t->density_quads : c->quads;
   const int expansion = t->expansion > 0 ? t->expansion : c->expansion;
@@ -742,6 +750,7 @@ int clue_set_tuning(clue_ctx* c, const clue_tuning* t) {
   c->bx = bx;
   c->by = by;
   c->lds_cap = cap;
+  c->plain_cap = plain_cap;
   c->r1 = r1;
   c->quads = quads;
   c->expansion = expansion;
@@ -756,6 +765,7 @@ int clue_get_tuning(const clue_ctx* c, clue_tuning* t, int32_t* halo) {
     t->block_x = c->g.bx;
     t->block_y = c->g.by;
     t->lds_cap = c->g.lds_cap;
+    t->plain_lds_cap = c->plain_cap > 0 ? c->plain_cap : c->g.lds_cap;
     t->nh_first_radius = c->g.nh_phase1 ? std::sqrt(c->g.r1sq) : 0.0f;
     t->density_quads = c->g.density_quads == 0 ? 2 : (c->g.density_quads == 2 ? 3 : 1);
     t->expansion = c->g.expand ? 2 : 1;

@@ -67,6 +67,8 @@ TUNINGS = [
     dict(nh_first_radius=3.99),
     dict(lds_cap=2048, block_x=16, block_y=16),
     dict(expansion=2),                        # k-way expansion: one thread per seed
+    dict(plain_lds_cap=64),                   # plain form: fallbacks; batched form: default cap
+    dict(lds_cap=64, plain_lds_cap=2048, block_x=16, block_y=16),
     dict(expansion=2, lds_cap=64, threads_per_query=4),
 ]
 
