@@ -188,6 +188,49 @@ def autotune(ctx, batch, n_events, params, *, reps=3, space=None, stage_times=Fa
     return dict(best, ms=best_ms), table
 
 
+def tune_plain_cap(ctx, event, caps=(768, 896, 960, 1024, 1280), reps=20, log=print):
+    """Picks the LDS cap of the plain form (one event per launch, fewer work
+    items in flight than a batch) by the median device time of ``event``
+    (dict of device tensors x, y, layer, energy) at each cap; every cap must
+    reproduce the first one's output. Leaves the best applied; returns it."""
+    import torch
+    stream = torch.cuda.current_stream()
+    n = int(event["x"].numel())
+    cid = torch.empty(n, dtype=torch.int32, device=event["x"].device)
+    seed = torch.empty(n, dtype=torch.uint8, device=event["x"].device)
+    ref = None
+    best, best_ms = None, None
+    for cap in caps:
+        ctx.set_tuning(plain_lds_cap=cap)
+
+        def run():
+            ctx.run(event["x"], event["y"], event["layer"], event["energy"], cid, seed)
+
+        run()
+        torch.cuda.synchronize()
+        ctx.status()
+        if ref is None:
+            ref = (cid.clone(), seed.clone())
+        elif not (torch.equal(cid, ref[0]) and torch.equal(seed, ref[1])):
+            raise RuntimeError(f"plain_lds_cap={cap} changed the clustering output")
+        ts = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            run()
+            e1.record(stream)
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ms = float(np.median(ts))
+        if log:
+            log(f"autotune plain lds_cap={cap}: {ms:.4f} ms")
+        if best_ms is None or ms < best_ms:
+            best, best_ms = cap, ms
+    ctx.set_tuning(plain_lds_cap=best)
+    return best
+
+
 def _freeze(t):
     return tuple(sorted((k, tuple(v) if isinstance(v, (list, tuple)) else v) for k, v in t.items()))
 
@@ -240,6 +283,10 @@ def _main():
     ctx = clue.Context(params["dc"], params["rho_c"], params["delta_c"], params["delta_o"], max_hits=b["x"].size,
                        max_events=args.events, extent=200.0, n_layers=100)
     best, table = autotune(ctx, batch, args.events, params, reps=args.reps, log=lambda s: print(s, flush=True))
+    # the plain form's cap, on the first event alone
+    n0 = int(evs[0]["x"].size)
+    first = {k: batch[k][:n0] for k in ("x", "y", "layer", "energy")}
+    best["plain_lds_cap"] = tune_plain_cap(ctx, first, log=lambda s: print(s, flush=True))
     key = cache_key(params, b["x"].size, args.events)
     store_cached(key, {k: v for k, v in best.items()}, args.out)
     print(_json.dumps({"key": key, "best": best}), flush=True)

@@ -144,3 +144,22 @@ def test_online_server_futures_equal_run():
                 ref = oracle.run_event(ev, p, n_threads=NT, want=())
                 assert np.array_equal(cid.cpu().numpy(), ref["cluster_id"])
         ctx.status()
+
+
+def test_plain_cap_tuner_keeps_outputs():
+    """The plain-form LDS cap tuner: every cap gives the same output (it
+    raises otherwise) and the chosen cap is applied."""
+    import torch
+    import paper_2001_09761_amd as clue
+    from paper_2001_09761_amd.autotune import tune_plain_cap
+    dev = torch.device("cuda", 0)
+    ev = gen.config4_event(0, n_layers=5)
+    p = _params(5)
+    t = to_dev(ev, dev)
+    with clue.Context(p["dc"], p["rho_c"], p["delta_c"], p["delta_o"], max_hits=ev["x"].size, extent=200.0,
+                      n_layers=5) as ctx:
+        cap = tune_plain_cap(ctx, t, caps=(96, 256, 960), reps=3, log=None)
+        assert cap in (96, 256, 960) and ctx.tuning()["plain_lds_cap"] == cap
+        cid, _ = ctx.run(t["x"], t["y"], t["layer"], t["energy"])
+        ref = oracle.run_event(ev, p, n_threads=NT, want=())
+        assert np.array_equal(cid.cpu().numpy(), ref["cluster_id"])
