@@ -1,9 +1,10 @@
 /*
  * A plain C consumer of the libclue C ABI (no Python, no torch), used by the
  * GPU test of the boundary. It reads one event from a binary file, clusters it
- * on HIP device 0 with clue_run and with clue_run_batch (one event), checks
- * that the two agree, checks two argument errors, and writes the cluster ids
- * and seed flags.
+ * on HIP device 0 with clue_run and with clue_run_batch (one event), again
+ * after a retuning through clue_set_tuning (the tuning struct as a C compiler
+ * lays it out), checks that all runs agree, checks two argument errors, and
+ * writes the cluster ids and seed flags.
  *
  * Input file:  int64 n; float dc, rho_c, delta_c, delta_o, x_min, y_min, x_max,
  *              y_max; int32 n_layers; float x[n]; float y[n]; int32 layer[n];
@@ -113,6 +114,35 @@ int main(int argc, char **argv) {
   if (memcmp(cid, cid2, n4) || memcmp(seed, seed2, (size_t)n)) {
     fprintf(stderr, "plain and batched forms disagree\n");
     return 3;
+  }
+
+  /* retune from C (small LDS caps force the fallback paths, k-way expansion)
+   * and run both forms again: the output must not change */
+  clue_tuning t;
+  int32_t halo = 0;
+  CHECK_CLUE(c, clue_get_tuning(c, &t, &halo));
+  if (t.lds_cap < 64 || t.block_x < 1 || halo < 1) return 2;
+  t.lds_cap = 96;
+  t.plain_lds_cap = 64;
+  t.expansion = 2;
+  t.nh_first_radius = -1.0f; /* keep */
+  CHECK_CLUE(c, clue_set_tuning(c, &t));
+  clue_tuning t2;
+  CHECK_CLUE(c, clue_get_tuning(c, &t2, &halo));
+  if (t2.lds_cap != 96 || t2.plain_lds_cap != 64 || t2.expansion != 2) return 2;
+  for (int form = 0; form < 2; ++form) {
+    CHECK_HIP(hipMemset(dcid, 0xff, n4));
+    if (form == 0)
+      CHECK_CLUE(c, clue_run(c, n, dx, dy, dl, de, dcid, dseed, NULL));
+    else
+      CHECK_CLUE(c, clue_run_batch(c, n, 1, dev_ids, dx, dy, dl, de, dcid, dseed, NULL));
+    CHECK_CLUE(c, clue_status(c, NULL));
+    CHECK_HIP(hipMemcpy(cid2, dcid, n4, hipMemcpyDeviceToHost));
+    CHECK_HIP(hipMemcpy(seed2, dseed, (size_t)n, hipMemcpyDeviceToHost));
+    if (memcmp(cid, cid2, n4) || memcmp(seed, seed2, (size_t)n)) {
+      fprintf(stderr, "the retuned %s form disagrees\n", form ? "batched" : "plain");
+      return 3;
+    }
   }
 
   /* argument errors come back as codes with a message, nothing is launched */
