@@ -163,3 +163,28 @@ def test_plain_cap_tuner_keeps_outputs():
         cid, _ = ctx.run(t["x"], t["y"], t["layer"], t["energy"])
         ref = oracle.run_event(ev, p, n_threads=NT, want=())
         assert np.array_equal(cid.cpu().numpy(), ref["cluster_id"])
+
+
+def test_online_server_validate_fails_only_the_bad_batch():
+    """With VALIDATE, an event holding a non-finite coordinate fails the
+    futures of its batch with CLUE_ERR_INPUT; the server keeps serving and
+    later events resolve normally."""
+    import torch
+    import paper_2001_09761_amd as clue
+    dev = torch.device("cuda", 0)
+    evs = _events(3, n_layers=4, seed=17)
+    p = _params(4)
+    bad = {k: v.copy() for k, v in evs[0].items() if isinstance(v, np.ndarray)}
+    bad["x"][5] = np.nan
+    cap = max(e["x"].size for e in evs)
+    with clue.Server(p["dc"], p["rho_c"], p["delta_c"], p["delta_o"], max_batch_hits=cap, max_batch_events=1,
+                     slots=1, extent=200.0, n_layers=4, flags=clue.VALIDATE) as srv:
+        f_bad = srv.submit(bad["x"], bad["y"], bad["layer"], bad["energy"])
+        with pytest.raises(clue.ClueError) as ei:
+            f_bad.result(timeout=60)
+        assert ei.value.code == -5
+        goods = [srv.submit(e["x"], e["y"], e["layer"], e["energy"]) for e in evs[1:]]
+        outs = [f.result(timeout=60) for f in goods]
+    for e, (cid, _) in zip(evs[1:], outs):
+        ref = oracle.run_event(e, p, n_threads=NT, want=())
+        assert np.array_equal(cid.cpu().numpy(), ref["cluster_id"])
