@@ -389,7 +389,7 @@ def _mean_counter(rows, counter, match, exclude=None):
     return sum(v) / len(v), len(v)
 
 
-def traffic_summary(d, stage, n_events):
+def traffic_summary(d, stage, n_events, out_path=None):
     """HBM bytes per launch of one stage's batched kernel: FETCH_SIZE and
     WRITE_SIZE (KiB per dispatch) averaged over its dispatches, each scaled by
     the ratio of known bytes to what the same counter reads for the 1 GiB
@@ -419,7 +419,7 @@ def traffic_summary(d, stage, n_events):
            "scale_fetch": sf, "scale_write": sw, "hbm_bytes_per_launch": hbm,
            "hbm_bytes_per_hit": hbm / hits, "alg_bytes_per_hit": ALG_BYTES[stage],
            "per_stage_hbm_bytes_per_launch": per_stage}
-    with open(PROFILE_TRAFFIC, "w") as fh:
+    with open(out_path or PROFILE_TRAFFIC, "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps(out))
 

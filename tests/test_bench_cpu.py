@@ -1,0 +1,61 @@
+"""bench.py's host logic on the CPU: the one-GPU guard, the reduction of
+rocprofv3 counter files to per-launch HBM traffic (copy-calibrated), and the
+tuning-to-arguments conversion."""
+import csv
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+FIELDS = ["Kernel_Name", "Counter_Name", "Counter_Value"]
+
+
+def _write(d, counter, rows):
+    os.makedirs(d, exist_ok=True)
+    with open(os.path.join(d, "run_counter_collection.csv"), "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=FIELDS)
+        w.writeheader()
+        for name, value in rows:
+            w.writerow({"Kernel_Name": name, "Counter_Name": counter, "Counter_Value": value})
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_traffic_summary_scales_by_the_copy_calibration(tmp_path):
+    # the copy reads and writes 1 GiB; its FETCH_SIZE reads half of that (scale 2), WRITE_SIZE all of it
+    gib_kib = float(1 << 20)
+    _write(tmp_path / "copy_fetch", "FETCH_SIZE", [("at::native::neg_kernel", gib_kib / 2)] * 3)
+    _write(tmp_path / "copy_write", "WRITE_SIZE", [("at::native::neg_kernel", gib_kib)] * 3)
+    dens = "void clue::k_density<true, 2, 0>(clue::DescArg<true>, clue::Geom, clue::Arena)"
+    lab = "void clue::k_label<true>(clue::DescArg<true>, clue::Geom, clue::Arena)"
+    _write(tmp_path / "fetch", "FETCH_SIZE", [(dens, 1000.0), (dens, 1200.0), (lab, 50.0),
+                                             ("void clue::k_density<false, 2, 0>(x)", 9e9)])
+    _write(tmp_path / "write", "WRITE_SIZE", [(dens, 300.0), (dens, 300.0), (lab, 25.0)])
+    out = tmp_path / "traffic.json"
+    bench.traffic_summary(str(tmp_path), "density", 32, out_path=str(out))
+    t = json.loads(out.read_text())
+    assert t["scale_fetch"] == pytest.approx(2.0) and t["scale_write"] == pytest.approx(1.0)
+    # mean over the batched density dispatches only (the plain one is excluded)
+    assert t["fetch_kib_per_dispatch"] == pytest.approx(1100.0)
+    assert t["hbm_bytes_per_launch"] == pytest.approx(1100.0 * 1024 * 2 + 300.0 * 1024)
+    assert t["hits_per_launch"] == 32 * 10 ** 6
+    assert t["per_stage_hbm_bytes_per_launch"]["labels"] == pytest.approx(50.0 * 1024 * 2 + 25.0 * 1024)
+    assert "grid_hist" not in t["per_stage_hbm_bytes_per_launch"]
+    assert t["kernel_source_sha"] == bench.kernel_source_sha()
+
+
+def test_tuning_kwargs():
+    t = {"block": (10, 8), "tile_size": 4.0, "lds_cap": 768, "plain_lds_cap": 960, "ms": 4.8, "density_quads": 1}
+    kw = bench.tuning_kwargs(t)
+    assert kw == {"block_x": 10, "block_y": 8, "tile_size": 4.0, "lds_cap": 768, "plain_lds_cap": 960,
+                  "density_quads": 1}
