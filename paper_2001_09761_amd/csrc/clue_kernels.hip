@@ -1517,8 +1517,16 @@ __global__ __launch_bounds__(kWG) void k_label(DescArg<G> dg, Geom g, Arena a) {
   const RunDesc d = dg.get();
   const bool fol = builds_lists(g);
   constexpr int U = kPlaceU;  // hits per lane per step, their chases interleaved
-  for (ChunkRun rn = xcd_run(d.n, kWG * U); rn.c < rn.end; rn.c += rn.step) {
-    const int sb = rn.c * kWG * U + (int)threadIdx.x;
+  constexpr int C = kWG * U;  // slots per chunk
+  // the chunk's parent, caller index and flags, staged in LDS: a nearest-higher
+  // lies within d_m, so most links stay inside the chunk. A staged parent may
+  // be older than a compression stored since; it is still an ancestor.
+  __shared__ int s_par[C];
+  __shared__ int s_hs[C];
+  __shared__ unsigned char s_fl[C];
+  for (ChunkRun rn = xcd_run(d.n, C); rn.c < rn.end; rn.c += rn.step) {
+    const int c0 = rn.c * C;
+    const int sb = c0 + (int)threadIdx.x;
     int s[U], p0[U], hsj[U], r[U], p[U];
     unsigned f[U];
     bool v[U];
@@ -1534,12 +1542,17 @@ __global__ __launch_bounds__(kWG) void k_label(DescArg<G> dg, Geom g, Arena a) {
         f[j] = a.flags[s[j]];
         hsj[j] = a.hs[s[j]];
       }
+      s_par[s[j] - c0] = p0[j];
+      s_hs[s[j] - c0] = hsj[j];
+      s_fl[s[j] - c0] = (unsigned char)f[j];
     }
+    __syncthreads();
+    auto staged = [&](int x) { return (unsigned)(x - c0) < (unsigned)C; };
     if (fol) {
 #pragma unroll
       for (int j = 0; j < U; ++j) {
         if (v[j] && (f[j] & F_FOLLOWER)) {
-          const int owner = a.hs[p0[j]];
+          const int owner = staged(p0[j]) ? s_hs[p0[j] - c0] : a.hs[p0[j]];
           a.flist[a.fstart[owner] + a.frank[s[j]]] = hsj[j];
         }
       }
@@ -1555,7 +1568,7 @@ __global__ __launch_bounds__(kWG) void k_label(DescArg<G> dg, Geom g, Arena a) {
       for (int j = 0; j < U; ++j) {
         if (p[j] != r[j]) {
           r[j] = p[j];
-          p[j] = ld_relaxed(&a.parent[r[j]]);
+          p[j] = staged(r[j]) ? s_par[r[j] - c0] : ld_relaxed(&a.parent[r[j]]);
           more = true;
         }
       }
@@ -1565,13 +1578,15 @@ __global__ __launch_bounds__(kWG) void k_label(DescArg<G> dg, Geom g, Arena a) {
     for (int j = 0; j < U; ++j) {
       if (!v[j]) continue;
       if (r[j] != s[j] && r[j] != p0[j]) st_relaxed(&a.parent[s[j]], r[j]);
+      const bool in = staged(r[j]);
       int lab = -1;
-      if (a.flags[r[j]] & F_SEED) {
+      if ((in ? s_fl[r[j] - c0] : a.flags[r[j]]) & F_SEED) {
         const int e = d.event ? clampi(d.event[hsj[j]] - d.event_base, 0, d.n_events - 1) : 0;
-        lab = a.seed_rank[a.hs[r[j]]] - a.seed_rank[event_first_hit(a, d, e)];
+        lab = a.seed_rank[in ? s_hs[r[j] - c0] : a.hs[r[j]]] - a.seed_rank[event_first_hit(a, d, e)];
       }
       d.cluster_id[hsj[j]] = lab;
     }
+    __syncthreads();  // the next chunk overwrites the staged arrays
   }
 }
 
