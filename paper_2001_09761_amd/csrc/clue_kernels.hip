@@ -242,22 +242,44 @@ template <bool G>
 __global__ __launch_bounds__(kWG) void k_place(DescArg<G> dg, Geom g, Arena a) {
   const RunDesc d = dg.get();
   const int* ids = reinterpret_cast<const int*>(a.rho);
-  for (ChunkRun rn = xcd_run(d.n, kWG); rn.c < rn.end; rn.c += rn.step) {
-    const int s = rn.c * kWG + (int)threadIdx.x;
-    if (s >= d.n) continue;
-    const int h = ids[s];
-    const int t = a.parent[s];
-    const float x = d.x[h], y = d.y[h], e = d.e[h];
-    const int s0 = a.tile_start[t], s1 = a.tile_start[t + 1];
-    int rk = 0;
-    int c = s0;
-    for (; c + 3 < s1; c += 4) rk += (ids[c] < h) + (ids[c + 1] < h) + (ids[c + 2] < h) + (ids[c + 3] < h);
-    for (; c < s1; ++c) rk += ids[c] < h;
-    const int slot = s0 + rk;
-    a.xs[slot] = x;
-    a.ys[slot] = y;
-    a.es[slot] = e;
-    a.hs[slot] = h;
+  constexpr int U = kPlaceU;
+  constexpr int C = kWG * U;  // slots per chunk
+  // the chunk's arrival-order ids in LDS: a hit's tile mostly lies inside
+  // the chunk, so most of its counting reads are LDS reads
+  __shared__ int s_ids[C];
+  for (ChunkRun rn = xcd_run(d.n, C); rn.c < rn.end; rn.c += rn.step) {
+    const int c0 = rn.c * C;
+    const int c1 = min(c0 + C, d.n);
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      const int sl = c0 + (int)threadIdx.x + j * kWG;
+      s_ids[sl - c0] = sl < d.n ? ids[sl] : 0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      const int sl = c0 + (int)threadIdx.x + j * kWG;
+      if (sl >= d.n) continue;
+      const int h = s_ids[sl - c0];
+      const int t = a.parent[sl];
+      const float x = d.x[h], y = d.y[h], e = d.e[h];
+      const int s0 = a.tile_start[t], s1 = a.tile_start[t + 1];
+      // the tile [s0, s1) in three parts: before the chunk, in it, after it
+      const int m0 = min(max(s0, c0), s1), m1 = max(min(s1, c1), m0);
+      int rk = 0;
+      for (int c = s0; c < m0; ++c) rk += ids[c] < h;
+      int c = m0;
+      for (; c + 3 < m1; c += 4)
+        rk += (s_ids[c - c0] < h) + (s_ids[c + 1 - c0] < h) + (s_ids[c + 2 - c0] < h) + (s_ids[c + 3 - c0] < h);
+      for (; c < m1; ++c) rk += s_ids[c - c0] < h;
+      for (c = m1; c < s1; ++c) rk += ids[c] < h;
+      const int slot = s0 + rk;
+      a.xs[slot] = x;
+      a.ys[slot] = y;
+      a.es[slot] = e;
+      a.hs[slot] = h;
+    }
+    __syncthreads();  // the next chunk overwrites the staged ids
   }
 }
 
@@ -1820,7 +1842,7 @@ static hipError_t launch_all(const Geom& g, const Arena& a, DescArg<G> dg, const
   mark();
   k_scatter<G><<<G ? cfg.persist_blocks_scatter : stream_grid(cdiv(n, kPlaceU)), kWG, 0, s>>>(dg, g, a);
   mark();
-  k_place<G><<<stream_grid(n), kWG, 0, s>>>(dg, g, a);
+  k_place<G><<<stream_grid(cdiv(n, kPlaceU)), kWG, 0, s>>>(dg, g, a);
   mark();
   const int lds = lds_bytes_for(g);
   if (g.kernel == 0) {
