@@ -1271,14 +1271,39 @@ __device__ __forceinline__ NhBest nh_start(float thr) { return NhBest{key64(__fl
 // One candidate j for query i: eligible when j is higher (ord/index keys);
 // keeps the lexicographic minimum of (d2, index), which starts at
 // nh_start(thr). d2 >= 0, so its bit pattern orders like its value.
-template <bool STRICT>
+// TRACK = false leaves b.p alone: the staged scan packs the LDS position into
+// the index word instead (see nh_pack).
+template <bool STRICT, bool TRACK = true>
 __device__ __forceinline__ void nh_consider(NhBest& b, float d2, unsigned ordj, unsigned hj, int pq, unsigned ordi,
                                             unsigned hi) {
   const bool higher = STRICT ? ordj > ordi : key64(ordj, hj) > key64(ordi, hi);
   const unsigned long long ck = key64(__float_as_uint(d2), hj);
   const bool take = higher & (ck < b.k);  // branch-free select
   b.k = take ? ck : b.k;
-  b.p = take ? pq : b.p;
+  if (TRACK) b.p = take ? pq : b.p;
+}
+
+// Staged records carry, in place of the caller index, the word
+// (event-local index << kPosBits) | LDS position. Within one event it orders
+// like the caller index, so the (rho, index) and (d2, index) keys compare as
+// before, and the winner's LDS position comes back out of its key: the scan
+// tracks no position of its own.
+constexpr int kPosBits = 11;
+constexpr unsigned kPosMask = (1u << kPosBits) - 1u;
+constexpr int kPackedEventMax = 1 << (32 - kPosBits);  // hits per event
+static_assert(kMaxLdsCap <= (1 << kPosBits), "an LDS position must fit the packed index word");
+__device__ __forceinline__ unsigned nh_pack(int h, int ev_first, int p) {
+  return ((unsigned)(h - ev_first) << kPosBits) | (unsigned)p;
+}
+__device__ __forceinline__ int nh_unpack_h(unsigned z, int ev_first) { return ev_first + (int)(z >> kPosBits); }
+// After a staged scan from key k0: a found winner gets its LDS position in
+// b.p and its caller index back in the key's low word.
+__device__ __forceinline__ void nh_unpack(NhBest& b, unsigned long long k0, int ev_first) {
+  if (b.p == -1 && b.k < k0) {
+    const unsigned z = (unsigned)(b.k & 0xffffffffu);
+    b.p = (int)(z & kPosMask);
+    b.k = key64((unsigned)(b.k >> 32), (unsigned)nh_unpack_h(z, ev_first));
+  }
 }
 
 __device__ __forceinline__ void nh_reduce(NhBest& b, int tpq) {
@@ -1325,17 +1350,17 @@ __device__ __forceinline__ void nh_scan_staged(const float4* __restrict__ rec, c
     // four independent LDS loads in flight per step
     for (; c < c4; c += 4 * step) {
       const float4 r0 = rec[c], r1 = rec[c + step], r2 = rec[c + 2 * step], r3 = rec[c + 3 * step];
-      nh_consider<STRICT>(b, dist2(xi, yi, r0.x, r0.y), __float_as_uint(r0.w), __float_as_uint(r0.z), c, ordi, hi);
-      nh_consider<STRICT>(b, dist2(xi, yi, r1.x, r1.y), __float_as_uint(r1.w), __float_as_uint(r1.z), c + step,
+      nh_consider<STRICT, false>(b, dist2(xi, yi, r0.x, r0.y), __float_as_uint(r0.w), __float_as_uint(r0.z), c, ordi, hi);
+      nh_consider<STRICT, false>(b, dist2(xi, yi, r1.x, r1.y), __float_as_uint(r1.w), __float_as_uint(r1.z), c + step,
                           ordi, hi);
-      nh_consider<STRICT>(b, dist2(xi, yi, r2.x, r2.y), __float_as_uint(r2.w), __float_as_uint(r2.z),
+      nh_consider<STRICT, false>(b, dist2(xi, yi, r2.x, r2.y), __float_as_uint(r2.w), __float_as_uint(r2.z),
                           c + 2 * step, ordi, hi);
-      nh_consider<STRICT>(b, dist2(xi, yi, r3.x, r3.y), __float_as_uint(r3.w), __float_as_uint(r3.z),
+      nh_consider<STRICT, false>(b, dist2(xi, yi, r3.x, r3.y), __float_as_uint(r3.w), __float_as_uint(r3.z),
                           c + 3 * step, ordi, hi);
     }
     for (; c < q1; c += step) {
       const float4 r = rec[c];
-      nh_consider<STRICT>(b, dist2(xi, yi, r.x, r.y), __float_as_uint(r.w), __float_as_uint(r.z), c, ordi, hi);
+      nh_consider<STRICT, false>(b, dist2(xi, yi, r.x, r.y), __float_as_uint(r.w), __float_as_uint(r.z), c, ordi, hi);
     }
   }
 }
@@ -1371,7 +1396,9 @@ __device__ __forceinline__ void nh_staged(const Geom& g, const Arena& a, const R
 #pragma unroll
     for (int k = 0; k < kStagePer; ++k) {
       const int p = base + (int)threadIdx.x + k * kWG;
-      if (p < R.total) rec[p] = make_float4(v[k].x, v[k].y, v[k].w, __uint_as_float(ord_f32(v[k].z)));
+      if (p < R.total)
+        rec[p] = make_float4(v[k].x, v[k].y, __uint_as_float(nh_pack(__float_as_int(v[k].w), ev_first, p)),
+                             __uint_as_float(ord_f32(v[k].z)));
     }
   }
   if (threadIdx.x == 0) *s_qn = 0;
@@ -1384,15 +1411,17 @@ __device__ __forceinline__ void nh_staged(const Geom& g, const Arena& a, const R
       int row, p;
       core_query(L, R, q, row, p);
       const float4 me = rec[p];
-      const unsigned ordi = __float_as_uint(me.w), hi = __float_as_uint(me.z);
+      const unsigned ordi = __float_as_uint(me.w), zi = __float_as_uint(me.z);
       const Window W = query_window(g, g.win_r1, me.x, me.y);
       const int tx0 = W.x0 - R.rx0, tx1 = W.x1 - R.rx0, ty0 = W.y0 - R.ry0, ty1 = W.y1 - R.ry0;
       if (tx0 >= 0 && ty0 >= 0 && tx1 < R.rw && ty1 < R.rh) {
         NhBest b = nh_start(g.r1sq);
-        nh_scan_staged<STRICT>(rec, L.ts, per_row, tx0, tx1, ty0, ty1, 0, 1, me.x, me.y, ordi, hi, b);
+        const unsigned long long k0 = b.k;
+        nh_scan_staged<STRICT>(rec, L.ts, per_row, tx0, tx1, ty0, ty1, 0, 1, me.x, me.y, ordi, zi, b);
+        nh_unpack(b, k0, ev_first);
         if (b.p >= 0) {
           b.p = slot_of(L, region_row_of(L, R.rh, b.p), b.p);
-          decide_and_store(g, a, d, slot_of(L, row, p), (int)hi, ord_inv(ordi), b, ev_first);
+          decide_and_store(g, a, d, slot_of(L, row, p), nh_unpack_h(zi, ev_first), ord_inv(ordi), b, ev_first);
           done = true;
         }
       }
@@ -1409,6 +1438,7 @@ __device__ __forceinline__ void nh_staged(const Geom& g, const Arena& a, const R
     const int qi = base + threadIdx.x / tpq;
     const bool active = qi < nu;
     NhBest b = nh_start(g.dm2);
+    const unsigned long long k0 = b.k;
     int slot = 0;
     unsigned hi = 0, ordi = 0;
     if (active) {
@@ -1417,17 +1447,20 @@ __device__ __forceinline__ void nh_staged(const Geom& g, const Arena& a, const R
       slot = slot_of(L, row, p);
       const float4 me = rec[p];
       ordi = __float_as_uint(me.w);
-      hi = __float_as_uint(me.z);
+      const unsigned zi = __float_as_uint(me.z);
+      hi = (unsigned)nh_unpack_h(zi, ev_first);
       const Window W = query_window(g, g.win_dm, me.x, me.y);
       const int tx0 = W.x0 - R.rx0, tx1 = W.x1 - R.rx0, ty0 = W.y0 - R.ry0, ty1 = W.y1 - R.ry0;
       if (tx0 >= 0 && ty0 >= 0 && tx1 < R.rw && ty1 < R.rh) {
-        nh_scan_staged<STRICT>(rec, L.ts, per_row, tx0, tx1, ty0, ty1, sub, tpq, me.x, me.y, ordi, hi, b);
+        nh_scan_staged<STRICT>(rec, L.ts, per_row, tx0, tx1, ty0, ty1, sub, tpq, me.x, me.y, ordi, zi, b);
       } else {
+        // global records carry the caller index itself, and the found slot as -2 - s
         atomicOr(a.err, (uint32_t)E_WINDOW);
         nh_global_scan<STRICT>(g, a, ubase, W, sub, tpq, me.x, me.y, ordi, hi, b);
       }
     }
-    nh_reduce(b, tpq);
+    nh_reduce(b, tpq);  // the lanes of one query all took the same branch
+    nh_unpack(b, k0, ev_first);
     if (active && sub == 0) {
       if (b.p >= 0)
         b.p = slot_of(L, region_row_of(L, R.rh, b.p), b.p);
@@ -1479,6 +1512,11 @@ __device__ __forceinline__ void nh_item(const Geom& g, const Arena& a, const Run
   region_setup(g, a, R, L);
   if (L.core_lo[R.ch] == 0) return;
   const int ev_first = event_first_hit(a, d, R.e);
+  if (event_first_hit(a, d, R.e + 1) - ev_first > kPackedEventMax) {
+    // an event too large for the packed index word takes the global-memory path
+    nh_global_region<STRICT>(g, a, d, R, L, ev_first);
+    return;
+  }
   if (R.total <= g.lds_cap) {
     nh_staged<STRICT>(g, a, d, R, L, rec, queue, s_qn, ev_first);
     return;

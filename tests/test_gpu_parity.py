@@ -246,3 +246,17 @@ def test_paper_sweep_batched():
     p = dict(gen.PAPER_PARAMS, extent=200.0, n_layers=100)
     got = gpu_run(batch, p, batched=True, n_events=10, tuning=dict(tile_size=gen.PAPER_BIN))
     assert_parity(got, _ref(batch, p), where="paper sweep batched")
+
+
+def test_events_at_and_beyond_packed_index_limit():
+    """The nearest-higher search packs (event-local index, LDS position) into
+    one word for events of up to 2**21 hits; larger events take the
+    global-memory path. One batch holds an event of exactly 2**21 hits and one
+    of 2.1M; the larger also runs alone in the plain form."""
+    at, p_at = gen.config2(seed=12, event_index=6, n_layers=128, hits_per_layer=16384)
+    beyond, p = gen.config2(seed=11, event_index=5, hits_per_layer=21000)
+    assert at["x"].size == 2 ** 21 and beyond["x"].size > 2 ** 21
+    p = dict(p, n_layers=128)
+    batch = gen.concat_events([at, beyond])
+    assert_parity(gpu_run(batch, p, batched=True, n_events=2), _ref(batch, p), where="2**21 and 2.1M batched")
+    assert_parity(gpu_run(beyond, p), _ref(beyond, p), where="2.1M plain")
