@@ -8,8 +8,11 @@
 namespace clue {
 
 constexpr int kWG = 256;            // threads per workgroup, every kernel
-constexpr int kScanItems = 16;      // elements per thread in the prefix scans
-constexpr int kScanChunk = kWG * kScanItems;
+constexpr int kScanItems = 16;      // elements per thread in the prefix scans of single launches
+constexpr int kScanItemsBatch = 64; // ... and of the persistent batched form, whose fewer, larger
+                                    // chunks shorten the look-back chains
+constexpr int kScanChunk = kWG * kScanItems;  // the smaller chunk, which sizes the status array
+__host__ __device__ constexpr int scan_items(bool graph) { return graph ? kScanItemsBatch : kScanItems; }
 constexpr int kMaxRegionTiles = 640;   // staged region tiles, rows x (cols + 1), per workgroup
 constexpr int kMaxRegionRows = 64;
 constexpr int kDefaultLdsCap = 960;    // staged hits per workgroup (fast path)

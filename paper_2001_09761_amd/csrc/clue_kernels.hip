@@ -122,8 +122,9 @@ __global__ __launch_bounds__(kWG) void k_clear(DescArg<G> dg, Geom g, Arena a) {
   for (int64_t i = i0; i < tt; i += stride) a.tile_start[i] = 0;
   if (fol)
     for (int64_t i = i0; i < n1; i += stride) a.fstart[i] = 0;
-  const int64_t nchunk_t = (tt + kScanChunk - 1) / kScanChunk;
-  const int64_t nchunk_s = (n1 + kScanChunk - 1) / kScanChunk;
+  constexpr int64_t SC = (int64_t)kWG * scan_items(G);
+  const int64_t nchunk_t = (tt + SC - 1) / SC;
+  const int64_t nchunk_s = (n1 + SC - 1) / SC;
   for (int64_t i = i0; i < nchunk_t && i < a.cap_chunks; i += stride) a.scan_status[i] = 0ull;
   for (int64_t i = i0; i < nchunk_s && i < a.cap_chunks; i += stride) a.scan_status[a.cap_chunks + i] = 0ull;
   for (int64_t i = i0; i < C_COUNT; i += stride) a.counters[i] = 0;
@@ -318,10 +319,11 @@ __device__ __forceinline__ int wave_sum(int v) {
 template <bool G, int KIND>
 __global__ __launch_bounds__(kWG) void k_scan(DescArg<G> dg, Geom g, Arena a) {
   constexpr int NCH = KIND == SCAN_SEEDS_FOLLOW ? 2 : 1;
+  constexpr int SI = scan_items(G), SC = kWG * SI;
   const RunDesc d = dg.get();
   const int64_t nel = KIND == SCAN_TILES ? (int64_t)d.n_events * g.L * g.tpl : (int64_t)d.n;
   const int64_t nout = nel + 1;  // the last output is the total
-  const int64_t nchunks = (nout + kScanChunk - 1) / kScanChunk;
+  const int64_t nchunks = (nout + SC - 1) / SC;
   unsigned long long* status = a.scan_status + (KIND == SCAN_TILES ? 0 : a.cap_chunks);
   int* ticket = &a.counters[KIND == SCAN_TILES ? C_TICKET_TILES : C_TICKET_SEEDS];
   const int lane = threadIdx.x & 63;
@@ -336,43 +338,48 @@ __global__ __launch_bounds__(kWG) void k_scan(DescArg<G> dg, Geom g, Arena a) {
     const int64_t chunk = s_chunk;
     __syncthreads();
     if (chunk >= nchunks) break;
-    const int64_t base = chunk * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+    const int64_t base = chunk * SC + (int64_t)threadIdx.x * SI;
 
-    int v[NCH][kScanItems];
+    int v[NCH][SI];
     if constexpr (KIND == SCAN_TILES) {
-      if (base + kScanItems <= nel) {
+      if (base + SI <= nel) {
         const int4* p = reinterpret_cast<const int4*>(a.tile_start + base);
 #pragma unroll
-        for (int q = 0; q < kScanItems / 4; ++q) {
+        for (int q = 0; q < SI / 4; ++q) {
           int4 w = p[q];
           v[0][4 * q] = w.x; v[0][4 * q + 1] = w.y; v[0][4 * q + 2] = w.z; v[0][4 * q + 3] = w.w;
         }
       } else {
 #pragma unroll
-        for (int i = 0; i < kScanItems; ++i) v[0][i] = base + i < nel ? a.tile_start[base + i] : 0;
+        for (int i = 0; i < SI; ++i) v[0][i] = base + i < nel ? a.tile_start[base + i] : 0;
       }
     } else {
       const bool aligned = ((uintptr_t)d.is_seed & 15u) == 0;
-      if (aligned && base + kScanItems <= nel) {
-        uint4 w = *reinterpret_cast<const uint4*>(d.is_seed + base);
-        const unsigned ww[4] = {w.x, w.y, w.z, w.w};
+      if (aligned && base + SI <= nel) {
+        static_assert(SI % 16 == 0, "the seed flags load in 16-byte words");
+        unsigned ww[SI / 4];
 #pragma unroll
-        for (int i = 0; i < kScanItems; ++i) v[0][i] = (ww[i >> 2] >> (8 * (i & 3))) & 0xffu ? 1 : 0;
+        for (int q = 0; q < SI / 16; ++q) {
+          const uint4 w = reinterpret_cast<const uint4*>(d.is_seed + base)[q];
+          ww[4 * q] = w.x; ww[4 * q + 1] = w.y; ww[4 * q + 2] = w.z; ww[4 * q + 3] = w.w;
+        }
+#pragma unroll
+        for (int i = 0; i < SI; ++i) v[0][i] = (ww[i >> 2] >> (8 * (i & 3))) & 0xffu ? 1 : 0;
       } else {
 #pragma unroll
-        for (int i = 0; i < kScanItems; ++i) v[0][i] = base + i < nel ? (d.is_seed[base + i] ? 1 : 0) : 0;
+        for (int i = 0; i < SI; ++i) v[0][i] = base + i < nel ? (d.is_seed[base + i] ? 1 : 0) : 0;
       }
       if constexpr (NCH == 2) {
-        if (base + kScanItems <= nel) {
+        if (base + SI <= nel) {
           const int4* p = reinterpret_cast<const int4*>(a.fstart + base);
 #pragma unroll
-          for (int q = 0; q < kScanItems / 4; ++q) {
+          for (int q = 0; q < SI / 4; ++q) {
             int4 w = p[q];
             v[1][4 * q] = w.x; v[1][4 * q + 1] = w.y; v[1][4 * q + 2] = w.z; v[1][4 * q + 3] = w.w;
           }
         } else {
 #pragma unroll
-          for (int i = 0; i < kScanItems; ++i) v[1][i] = base + i < nel ? a.fstart[base + i] : 0;
+          for (int i = 0; i < SI; ++i) v[1][i] = base + i < nel ? a.fstart[base + i] : 0;
         }
       }
     }
@@ -382,7 +389,7 @@ __global__ __launch_bounds__(kWG) void k_scan(DescArg<G> dg, Geom g, Arena a) {
     for (int c = 0; c < NCH; ++c) {
       int acc = 0;
 #pragma unroll
-      for (int i = 0; i < kScanItems; ++i) {
+      for (int i = 0; i < SI; ++i) {
         int t = v[c][i];
         v[c][i] = acc;
         acc += t;
@@ -456,14 +463,14 @@ __global__ __launch_bounds__(kWG) void k_scan(DescArg<G> dg, Geom g, Arena a) {
     for (int c = 0; c < NCH; ++c) {
       const int off = s_prefix[c] + wbase[c] + texcl[c];
       int* out = KIND == SCAN_TILES ? a.tile_start : (c == 0 ? a.seed_rank : a.fstart);
-      if (base + kScanItems <= nout) {
+      if (base + SI <= nout) {
         int4* p = reinterpret_cast<int4*>(out + base);
 #pragma unroll
-        for (int q = 0; q < kScanItems / 4; ++q)
+        for (int q = 0; q < SI / 4; ++q)
           p[q] = make_int4(off + v[c][4 * q], off + v[c][4 * q + 1], off + v[c][4 * q + 2], off + v[c][4 * q + 3]);
       } else {
 #pragma unroll
-        for (int i = 0; i < kScanItems; ++i)
+        for (int i = 0; i < SI; ++i)
           if (base + i < nout) out[base + i] = off + v[c][i];
       }
     }
