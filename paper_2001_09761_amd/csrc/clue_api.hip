@@ -303,8 +303,9 @@ static int alloc_arena(clue_ctx* c, int64_t N, int32_t E) {
   if (c->arena_base) {
     HIP_TRY(c, hipDeviceSynchronize());
     drop_graph(c);
-    hipFree(c->arena_base);
+    void* old = c->arena_base;
     c->arena_base = nullptr;
+    HIP_TRY(c, hipFree(old));
   }
   hipError_t e = hipMalloc(&c->arena_base, P.total);
   if (e != hipSuccess) {
@@ -331,14 +332,14 @@ static int ensure_graph(clue_ctx* c) {
   hipGraph_t graph = nullptr;
   hipError_t ce = hipStreamEndCapture(c->cap_stream, &graph);
   if (le != hipSuccess) {
-    if (graph) hipGraphDestroy(graph);
+    if (graph) (void)hipGraphDestroy(graph);  // the launch error is the one reported
     return hip_fail(c, le, "launch during capture");
   }
   if (ce != hipSuccess) return hip_fail(c, ce, "hipStreamEndCapture");
   hipGraphExec_t exec = nullptr;
   hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
   if (ie != hipSuccess) {
-    hipGraphDestroy(graph);
+    (void)hipGraphDestroy(graph);  // the instantiation error is the one reported
     return hip_fail(c, ie, "hipGraphInstantiate");
   }
   c->graph = graph;
@@ -554,8 +555,9 @@ static int ensure_staging(clue_ctx* c) {
   HIP_TRY(c, hipSetDevice(c->device));
   if (c->stage_base) {
     HIP_TRY(c, hipDeviceSynchronize());
-    hipFree(c->stage_base);
+    void* old = c->stage_base;
     c->stage_base = nullptr;
+    HIP_TRY(c, hipFree(old));
   }
   const size_t n = (size_t)c->a.cap_hits;
   auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
@@ -643,7 +645,7 @@ int clue_run_batch_host(clue_ctx* c, int64_t n, int32_t n_events, const int32_t*
     else
       rc = run_common(c, nh, 1, 0, nullptr, sc.x, sc.y, sc.layer, sc.e, sc.cid, sc.seed, c->comp, true);
     if (rc != CLUE_OK) {
-      hipDeviceSynchronize();
+      (void)hipDeviceSynchronize();  // drain the copies in flight; rc is the error reported
       return rc;
     }
     HIP_TRY(c, hipEventRecord(c->done[slot], c->comp));
@@ -800,21 +802,23 @@ const char* clue_last_error(const clue_ctx* c) {
   return c->err.c_str();
 }
 
+// Teardown has no caller to report to: every release is attempted, and their
+// status codes are deliberately dropped.
 void clue_destroy(clue_ctx* c) {
   if (!c) return;
-  hipSetDevice(c->device);
-  hipDeviceSynchronize();
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
   drop_graph(c);
-  if (c->cap_stream) hipStreamDestroy(c->cap_stream);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (hipStream_t st : {c->h2d, c->comp, c->d2h})
-    if (st) hipStreamDestroy(st);
+    if (st) (void)hipStreamDestroy(st);
   for (int i = 0; i < 2; ++i)
     for (hipEvent_t e : {c->in_ready[i], c->done[i], c->out_done[i]})
-      if (e) hipEventDestroy(e);
-  if (c->stage_base) hipFree(c->stage_base);
+      if (e) (void)hipEventDestroy(e);
+  if (c->stage_base) (void)hipFree(c->stage_base);
   for (int i = 0; i <= S_COUNT; ++i)
-    if (c->ev[i]) hipEventDestroy(c->ev[i]);
-  if (c->arena_base) hipFree(c->arena_base);
+    if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+  if (c->arena_base) (void)hipFree(c->arena_base);
   delete c;
 }
 
