@@ -260,3 +260,14 @@ def test_events_at_and_beyond_packed_index_limit():
     batch = gen.concat_events([at, beyond])
     assert_parity(gpu_run(batch, p, batched=True, n_events=2), _ref(batch, p), where="2**21 and 2.1M batched")
     assert_parity(gpu_run(beyond, p), _ref(beyond, p), where="2.1M plain")
+
+
+@pytest.mark.parametrize("n", [4095, 4096, 16383, 16384, 16385])
+def test_scan_chunk_boundaries(n):
+    """Seed numbering scans n + 1 elements in chunks of 256 threads x 16
+    elements (plain launches) or x 64 (the batched form): hit counts whose
+    n + 1 lands exactly on, or one past, a chunk edge of either form."""
+    ev, p = gen.config2(seed=20 + n % 7, event_index=n, n_layers=1, hits_per_layer=n)
+    ref = _ref(ev, p)
+    assert_parity(gpu_run(ev, p), ref, where=f"n={n} plain")
+    assert_parity(gpu_run(ev, p, batched=True), ref, where=f"n={n} batched")
