@@ -243,7 +243,7 @@ template <bool G>
 __global__ __launch_bounds__(kWG) void k_place(DescArg<G> dg, Geom g, Arena a) {
   const RunDesc d = dg.get();
   const int* ids = reinterpret_cast<const int*>(a.rho);
-  constexpr int U = kPlaceU;
+  constexpr int U = G ? kBatchU : kPlaceU;
   constexpr int C = kWG * U;  // slots per chunk
   // the chunk's arrival-order ids in LDS: a hit's tile mostly lies inside
   // the chunk, so most of its counting reads are LDS reads
@@ -1583,7 +1583,7 @@ template <bool G>
 __global__ __launch_bounds__(kWG) void k_label(DescArg<G> dg, Geom g, Arena a) {
   const RunDesc d = dg.get();
   const bool fol = builds_lists(g);
-  constexpr int U = G ? kLabelU : kPlaceU;  // hits per lane per step, their chases interleaved
+  constexpr int U = G ? kBatchU : kPlaceU;  // hits per lane per step, their chases interleaved
   constexpr int C = kWG * U;  // slots per chunk
   // the chunk's parent, caller index and flags, staged in LDS: a nearest-higher
   // lies within d_m, so most links stay inside the chunk. A staged parent may
@@ -1887,7 +1887,7 @@ static hipError_t launch_all(const Geom& g, const Arena& a, DescArg<G> dg, const
   mark();
   k_scatter<G><<<G ? cfg.persist_blocks_scatter : stream_grid(cdiv(n, kPlaceU)), kWG, 0, s>>>(dg, g, a);
   mark();
-  k_place<G><<<stream_grid(cdiv(n, kPlaceU)), kWG, 0, s>>>(dg, g, a);
+  k_place<G><<<stream_grid(cdiv(n, G ? kBatchU : kPlaceU)), kWG, 0, s>>>(dg, g, a);
   mark();
   const int lds = lds_bytes_for(g);
   if (g.kernel == 0) {
@@ -1922,7 +1922,7 @@ static hipError_t launch_all(const Geom& g, const Arena& a, DescArg<G> dg, const
     const int g_dfs = G ? cfg.persist_blocks_stream : std::min(stream_grid(n), std::max(1, cfg.persist_blocks_stream));
     k_expand_dfs<G><<<g_dfs, kWG, 0, s>>>(dg, g, a);
   } else {
-    k_label<G><<<stream_grid(cdiv(n, G ? kLabelU : kPlaceU)), kWG, 0, s>>>(dg, g, a);
+    k_label<G><<<stream_grid(cdiv(n, G ? kBatchU : kPlaceU)), kWG, 0, s>>>(dg, g, a);
   }
   mark();
   if (fol) k_follow_sort<G><<<stream_grid(cdiv(n, kPlaceU)), kWG, 0, s>>>(dg, g, a);
