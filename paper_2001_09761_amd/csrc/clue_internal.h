@@ -22,9 +22,10 @@ constexpr int kMaxLdsCap = 2048;
 __host__ __device__ constexpr int lds_records_density(int lds_cap) { return (lds_cap * (16 + 2 + 8) + 15) & ~15; }
 constexpr int kStagePer = 4;       // staged hits per lane per round (loads in flight)
 constexpr int kPlaceU = 4;         // hits per lane per step of the streaming grid-build and list kernels
-constexpr int kBatchU = 8;         // ... and of the batched k_place and k_label, whose 2048-slot LDS
-                                   // chunks keep more of a tile or a parent chain on chip (single
-                                   // launches keep kPlaceU, for more workgroups per event)
+constexpr int kBatchU = 8;         // ... and of the batched k_scatter, k_place and k_label: longer runs
+                                   // per workgroup, and 2048-slot LDS chunks that keep more of a tile
+                                   // or a parent chain on chip (single launches keep kPlaceU, for more
+                                   // workgroups per event)
 constexpr int kScatterBlocksPerCU = 2;  // persistent k_scatter workgroups per CU
 
 // Counters in device memory, cleared at the start of every run. Each sits on

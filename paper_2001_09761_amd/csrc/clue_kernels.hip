@@ -215,7 +215,7 @@ template <bool G>
 __global__ __launch_bounds__(kWG) void k_scatter(DescArg<G> dg, Geom g, Arena a) {
   const RunDesc d = dg.get();
   int* ids = reinterpret_cast<int*>(a.rho);
-  constexpr int U = kPlaceU;
+  constexpr int U = G ? kBatchU : kPlaceU;
   for (ChunkRun rn = xcd_run(d.n, kWG * U); rn.c < rn.end; rn.c += rn.step) {
     const int h0 = rn.c * kWG * U + (int)threadIdx.x;
     int t[U], r[U];
