@@ -29,6 +29,12 @@ def load_cases(path=GOLDEN):
                 b = rhs.split()
                 cur["hits"].append((float(a[0]), float(a[1]), int(a[2]), float(a[3])))
                 cur["expect"].append((float(b[0]), int(b[1]), int(b[2]), int(b[3])))
+            elif tok[0] == "followers":
+                # F_i of Eq. 5 for one owner i, or "none": every list empty
+                cur.setdefault("followers", {})
+                if tok[1].strip() != "none":
+                    owner, rest = tok[1].split(":")
+                    cur["followers"][int(owner)] = [int(v) for v in rest.split()]
             elif tok[0] == "end":
                 h = cur["hits"]
                 e = cur["expect"]
@@ -42,6 +48,14 @@ def load_cases(path=GOLDEN):
                 cur["nh"] = np.array([t[1] for t in e], np.int32)
                 cur["cluster_id"] = np.array([t[2] for t in e], np.int32)
                 cur["is_seed"] = np.array([t[3] for t in e], np.uint8)
+                assert "followers" in cur, f"case {cur['name']} states no follower lists"
+                fs = [0]
+                fl = []
+                for i in range(len(h)):
+                    fl.extend(cur["followers"].get(i, []))
+                    fs.append(len(fl))
+                cur["fstart"] = np.array(fs, np.int32)
+                cur["flist"] = np.array(fl, np.int32)
                 cases.append(cur)
                 cur = None
     return cases

@@ -24,6 +24,33 @@ def test_hand_case(case, brute):
     assert np.array_equal(o["nh"], case["nh"]), (o["nh"], case["nh"])
     assert np.array_equal(o["cluster_id"], case["cluster_id"]), (o["cluster_id"], case["cluster_id"])
     assert np.array_equal(o["is_seed"], case["is_seed"])
+    # follower lists F_i (Eq. 5), written out by hand in the fixture
+    assert np.array_equal(o["fstart"], case["fstart"]), (o["fstart"], case["fstart"])
+    assert np.array_equal(o["flist"], case["flist"]), (o["flist"], case["flist"])
+
+
+def test_hand_cases_as_one_batch():
+    """The hand cases that share one parameter set, run as consecutive events
+    of one batch: every output stays event-local (nh, follower entries, ids
+    from 0 per event) and the follower CSR offsets run over the whole batch.
+    The expected CSR is assembled here from the hand-written per-case lists."""
+    p0 = CASES[0]["params"]
+    group = [c for c in CASES if c["params"] == p0]
+    assert len(group) >= 5 and any(len(c["flist"]) >= 4 for c in group)
+    cat = {k: np.concatenate([c["event"][k] for c in group]) for k in ("x", "y", "layer", "energy")}
+    event = np.concatenate([np.full(c["event"]["x"].size, i, np.int32) for i, c in enumerate(group)])
+    o = oracle.run(cat["x"], cat["y"], cat["layer"], cat["energy"], event=event, n_events=len(group),
+                   dc=p0["dc"], rho_c=p0["rho_c"], delta_c=p0["delta_c"], delta_o=p0["delta_o"],
+                   bounds=p0["bounds"], n_layers=p0["n_layers"], n_threads=3)
+    fstart = [0]
+    for c in group:
+        fstart.extend((fstart[-1] + c["fstart"][1:]).tolist())
+    flist = np.concatenate([c["flist"] for c in group])
+    assert np.array_equal(o["fstart"], np.array(fstart, np.int32))
+    assert np.array_equal(o["flist"], flist)
+    assert np.array_equal(o["nh"], np.concatenate([c["nh"] for c in group]))
+    assert np.array_equal(o["cluster_id"], np.concatenate([c["cluster_id"] for c in group]))
+    assert np.array_equal(o["n_clusters"], np.array([c["is_seed"].sum() for c in group], np.int32))
 
 
 def _lattice(nx, ny, pitch=1.0):

@@ -85,15 +85,24 @@ def test_invariants_hard_variant_small(dc):
     check_invariants(ev, o, p)
 
 
-@pytest.mark.parametrize("which", ["config1", "config2_small", "hard_dc3"])
+FP64_CASES = ["config1", "config2", "hard_dc1", "hard_dc2", "hard_dc3", "config4_ev0"]
+
+
+@pytest.mark.parametrize("which", FP64_CASES)
 def test_fp64_error(which):
+    """P7 (Eq. 3): the binary32 density against the same neighbour set summed
+    in binary64, at the full size of every benchmarked workload (1M hits for
+    configs 2 and 3). Stated requirement: max relative error <= 1e-6."""
     if which == "config1":
         ev, p = gen.config1()
-    elif which == "config2_small":
-        ev, p = gen.config2(n_layers=5)
+    elif which == "config2":
+        ev, p = gen.config2()
+    elif which.startswith("hard_dc"):
+        ev, p = gen.config3_hard(float(which[-1]))
     else:
-        ev, p = gen.config3_hard(3.0, n_layers=3)
-    o = oracle.run_event(ev, p)
+        ev = gen.config4_event(0)
+        p = dict(gen.DEFAULT_PARAMS, extent=200.0, n_layers=100)
+    o = oracle.run_event(ev, p, n_threads=8, want=("rho", "rho64"))
     # Sequential float32 summation of m non-negative terms has relative error
     # at most gamma_{m-1} = (m-1)u / (1-(m-1)u), u = 2^-24 (Higham, Accuracy
     # and Stability of Numerical Algorithms, Sec. 4.2); the double reference
@@ -102,13 +111,12 @@ def test_fp64_error(which):
     # neighbourhood size m per hit from unit weights
     ones = oracle.run(ev["x"], ev["y"], ev["layer"], np.ones_like(ev["energy"]), dc=p["dc"], rho_c=1,
                       delta_c=p["delta_c"], delta_o=p["delta_o"], extent=p["extent"],
-                      n_layers=p["n_layers"], want=("rho",))
+                      n_layers=p["n_layers"], want=("rho",), n_threads=8)
     m = ones["rho"].astype(np.float64)
     u = 2.0 ** -24
     gamma = (m - 1) * u / (1 - (m - 1) * u)
     assert np.all(rel <= gamma + u), float(np.max(rel - gamma))
-    if which != "hard_dc3":
-        assert rel.max() <= 1e-6
+    assert rel.max() <= 1e-6, (which, float(rel.max()), int(m.max()))
 
 
 def test_delta_o_monotone_noise():
