@@ -1384,12 +1384,16 @@ __device__ __forceinline__ void nh_global_scan(const Geom& g, const Arena& a, in
   }
 }
 
+// Returns false, having written nothing, when a staged hit's event-local
+// index does not fit the packed word; the caller then searches the region in
+// global memory.
 template <bool STRICT>
-__device__ __forceinline__ void nh_staged(const Geom& g, const Arena& a, const RunDesc& d, const Region& R, const RegionLds& L,
+__device__ __forceinline__ bool nh_staged(const Geom& g, const Arena& a, const RunDesc& d, const Region& R, const RegionLds& L,
                           float4* rec, int* queue, int* s_qn, int ev_first) {
   const int per_row = R.rw + 1;
   const int64_t ubase = (int64_t)R.unit * g.tpl;
   // every global load of a lane is issued before its first LDS store
+  bool outside = false;  // a hit whose event-local index does not fit the packed word
   for (int base = 0; base < R.total; base += kStagePer * kWG) {
     float4 v[kStagePer];
 #pragma unroll
@@ -1403,13 +1407,18 @@ __device__ __forceinline__ void nh_staged(const Geom& g, const Arena& a, const R
 #pragma unroll
     for (int k = 0; k < kStagePer; ++k) {
       const int p = base + (int)threadIdx.x + k * kWG;
-      if (p < R.total)
+      if (p < R.total) {
+        outside |= (unsigned)(__float_as_int(v[k].w) - ev_first) >= (unsigned)kPackedEventMax;
         rec[p] = make_float4(v[k].x, v[k].y, __uint_as_float(nh_pack(__float_as_int(v[k].w), ev_first, p)),
                              __uint_as_float(ord_f32(v[k].z)));
+      }
     }
   }
   if (threadIdx.x == 0) *s_qn = 0;
-  __syncthreads();
+  // Event ids that decrease (unvalidated input) can leave hits of this unit
+  // before its event's first hit; their packed index would wrap. Such a
+  // region is searched in global memory, where records carry caller indices.
+  if (__syncthreads_or(outside)) return false;
   const int nq = L.core_lo[R.ch];
   // phase 1: radius r1; only hits strictly within r1 can settle a query here
   for (int q = threadIdx.x; q < nq; q += kWG) {
@@ -1476,6 +1485,7 @@ __device__ __forceinline__ void nh_staged(const Geom& g, const Arena& a, const R
       decide_and_store(g, a, d, slot, (int)hi, ord_inv(ordi), b, ev_first);
     }
   }
+  return true;
 }
 
 template <bool STRICT>
@@ -1525,7 +1535,7 @@ __device__ __forceinline__ void nh_item(const Geom& g, const Arena& a, const Run
     return;
   }
   if (R.total <= g.lds_cap) {
-    nh_staged<STRICT>(g, a, d, R, L, rec, queue, s_qn, ev_first);
+    if (!nh_staged<STRICT>(g, a, d, R, L, rec, queue, s_qn, ev_first)) nh_global_region<STRICT>(g, a, d, R, L, ev_first);
     return;
   }
   // too dense: the four quarter blocks, then single tiles
@@ -1536,8 +1546,9 @@ __device__ __forceinline__ void nh_item(const Geom& g, const Arena& a, const Run
       make_region(g, unit, sx, sy, ex, ey, R);
       region_setup(g, a, R, L);
       if (L.core_lo[R.ch] == 0) continue;
+      if (R.total <= g.lds_cap && nh_staged<STRICT>(g, a, d, R, L, rec, queue, s_qn, ev_first)) continue;
       if (R.total <= g.lds_cap) {
-        nh_staged<STRICT>(g, a, d, R, L, rec, queue, s_qn, ev_first);
+        nh_global_region<STRICT>(g, a, d, R, L, ev_first);
         continue;
       }
       for (int ty = sy; ty <= ey; ++ty)
@@ -1545,9 +1556,7 @@ __device__ __forceinline__ void nh_item(const Geom& g, const Arena& a, const Run
           make_region(g, unit, tx, ty, tx, ty, R);
           region_setup(g, a, R, L);
           if (L.core_lo[R.ch] == 0) continue;
-          if (R.total <= g.lds_cap)
-            nh_staged<STRICT>(g, a, d, R, L, rec, queue, s_qn, ev_first);
-          else
+          if (!(R.total <= g.lds_cap && nh_staged<STRICT>(g, a, d, R, L, rec, queue, s_qn, ev_first)))
             nh_global_region<STRICT>(g, a, d, R, L, ev_first);
         }
     }

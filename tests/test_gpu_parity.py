@@ -35,6 +35,7 @@ def test_hand_cases(case, batched):
     assert np.array_equal(got["nh"], case["nh"])
     assert np.array_equal(got["cluster_id"], case["cluster_id"])
     assert np.array_equal(got["is_seed"], case["is_seed"])
+    assert np.array_equal(got["fstart"], case["fstart"]) and np.array_equal(got["flist"], case["flist"])
 
 
 ADV_P = dict(dc=2.0, rho_c=5.0, delta_c=2.0, delta_o=4.0, bounds=(0, 0, 20, 20), n_layers=3)
@@ -100,7 +101,7 @@ def test_config2_shuffled():
     assert_parity(gpu_run(ev, p), _ref(ev, p), where="cfg2 shuffled")
 
 
-@pytest.mark.parametrize("step", [1, 4, 10])
+@pytest.mark.parametrize("step", range(1, 11))
 def test_config3_sweep(step):
     ev, p = gen.config3_sweep(step)
     assert_parity(gpu_run(ev, p, followers=False), _ref(ev, p, want=("rho", "nh", "delta2")),
@@ -271,3 +272,37 @@ def test_scan_chunk_boundaries(n):
     ref = _ref(ev, p)
     assert_parity(gpu_run(ev, p), ref, where=f"n={n} plain")
     assert_parity(gpu_run(ev, p, batched=True), ref, where=f"n={n} batched")
+
+
+def test_decreasing_event_ids_without_validation():
+    """Event ids that decrease break the batched form's contract; without
+    CLUE_VALIDATE the result is unspecified but the run must stay within its
+    buffers. Here the first event's hits resume after the second's, so the
+    second event's recorded first hit can lie past its own hits (the packed
+    nearest-higher index would wrap; such regions take the global search).
+    The run completes, reports no device error, and the context then clusters
+    a valid batch bit-exactly."""
+    import torch
+    import paper_2001_09761_amd as clue
+    from gpu_helpers import to_dev
+    a = adversarial_event(21, n=3000, n_layers=2)
+    b = adversarial_event(22, n=2000, n_layers=2)
+    ev = {k: np.concatenate([a[k][:1500], b[k], a[k][1500:]]) for k in ("x", "y", "layer", "energy")}
+    ev["event"] = np.r_[np.zeros(1500, np.int32), np.ones(2000, np.int32), np.zeros(1500, np.int32)]
+    n = ev["x"].size
+    p = dict(ADV_P, n_layers=2)
+    dev = torch.device("cuda", 0)
+    t = to_dev(ev, dev)
+    with clue.Context(p["dc"], p["rho_c"], p["delta_c"], p["delta_o"], max_hits=n, max_events=2,
+                      bounds=p["bounds"], n_layers=2, flags=clue.KEEP_INTERMEDIATES) as ctx:
+        for _ in range(3):
+            cid, seed = ctx.run_batch(t["event"], 2, t["x"], t["y"], t["layer"], t["energy"])
+            fs, fl = ctx.followers()
+            torch.cuda.synchronize()
+            ctx.status()
+            assert set(np.unique(seed.cpu().numpy())) <= {0, 1}
+            f = fs.cpu().numpy()
+            assert f[0] == 0 and np.all(np.diff(f) >= 0) and f[-1] <= n
+        good = gen.concat_events([a, b])
+        got = gpu_run(good, p, batched=True, n_events=2, ctx=ctx)
+    assert_parity(got, _ref(good, p), where="valid batch after decreasing ids")

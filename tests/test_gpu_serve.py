@@ -30,8 +30,9 @@ def test_served_results_equal_alone_and_oracle():
     import paper_2001_09761_amd as clue
     from paper_2001_09761_amd.serve import GpuPoolBackend, Scheduler, make_pool
     dev = torch.device("cuda", 0)
-    evs = _events(40)
-    p = _params(8)
+    evs = _events(40, n_layers=100)  # config-5 events: 100 layers x U[1000, 10000] hits
+    p = _params(100)
+    print(f"served parity: {len(evs)} events, {sum(e['x'].size for e in evs)} hits", flush=True)
     pool = make_pool(evs, dev)
     n_hits = [e["x"].size for e in evs]
     cap = 12 * max(n_hits)
@@ -44,16 +45,16 @@ def test_served_results_equal_alone_and_oracle():
     got_cid = pool["cluster_id"].cpu().numpy()
     got_seed = pool["is_seed"].cpu().numpy()
     with clue.Context(p["dc"], p["rho_c"], p["delta_c"], p["delta_o"], max_hits=max(n_hits), extent=200.0,
-                      n_layers=8) as ctx:
+                      n_layers=100) as ctx:
         for i, ev in enumerate(evs):
             a, z = int(pool["offsets"][i]), int(pool["offsets"][i + 1])
             t = to_dev(ev, dev)
             cid, seed = ctx.run(t["x"], t["y"], t["layer"], t["energy"])
             assert np.array_equal(got_cid[a:z], cid.cpu().numpy()), f"event {i} differs in the mix"
             assert np.array_equal(got_seed[a:z], seed.cpu().numpy()), f"event {i} seeds differ in the mix"
-            if i % 8 == 0:
-                ref = oracle.run_event(ev, p, n_threads=NT, want=())
-                assert np.array_equal(got_cid[a:z], ref["cluster_id"])
+            ref = oracle.run_event(ev, p, n_threads=NT, want=())
+            assert np.array_equal(got_cid[a:z], ref["cluster_id"]), f"event {i} differs from the oracle"
+            assert np.array_equal(got_seed[a:z], ref["is_seed"]), f"event {i} seeds differ from the oracle"
         ctx.status()
     be.close()
 
