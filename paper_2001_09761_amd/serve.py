@@ -15,8 +15,11 @@ Slots run concurrently on separate streams, so batches overlap on the GPU
 while new events keep arriving. Latency is completion minus arrival.
 
 The scheduling logic is backend-independent: ``GpuPoolBackend`` drives the
-HIP library on a device-resident event pool; tests also drive it with a CPU
-backend and a virtual clock.
+HIP library on a device-resident event pool; ``GpuStagedBackend`` keeps the
+events in pinned host memory and admission copies each one into a bounded
+device staging ring sized from the HBM budget (the host-resident serving
+variant: an event that finds no room waits in the queue); tests also drive the
+scheduler with a CPU backend and a virtual clock.
 
 ``Server`` is the online form of the same loop: callers ``submit`` events as
 they come and receive futures of their cluster ids.
@@ -60,8 +63,12 @@ class RunStats:
     def latencies(self):
         return np.array([r.t_done - r.t_arrival for r in self.records], dtype=float)
 
+    def admission_waits(self):
+        return np.array([r.t_admit - r.t_arrival for r in self.records], dtype=float)
+
     def summary(self):
         lat = self.latencies()
+        wait = self.admission_waits()
         hits = sum(r.n_hits for r in self.records)
         t0 = min(r.t_arrival for r in self.records)
         t1 = max(r.t_done for r in self.records)
@@ -72,11 +79,77 @@ class RunStats:
                     mean_ms=float(lat.mean() * 1e3), batches=len(self.batches),
                     mean_batch_events=float(np.mean(sizes)) if sizes else 0.0,
                     max_batch_events=int(max(sizes)) if sizes else 0,
-                    max_inflight_bytes=int(self.max_inflight_bytes), failures=self.failures)
+                    max_inflight_bytes=int(self.max_inflight_bytes), failures=self.failures,
+                    admit_wait_p50_ms=float(np.percentile(wait, 50) * 1e3),
+                    admit_wait_p99_ms=float(np.percentile(wait, 99) * 1e3))
+
+
+class StagingRing:
+    """Contiguous hit ranges of a fixed-capacity device region, given out in
+    admission (FIFO) order and freed in any order: a freed range is reused once
+    every older range is free too. A range that does not fit before the end
+    of the region starts again at offset 0, so every range is contiguous."""
+
+    def __init__(self, capacity_hits):
+        self.capacity = int(capacity_hits)
+        self.live = deque()   # [event, offset, hits, done] in admission order
+        self.where = {}       # event -> its entry
+
+    def allocate(self, event, n_hits):
+        n = int(n_hits)
+        if n > self.capacity:
+            raise ValueError(f"event of {n} hits exceeds the staging capacity ({self.capacity})")
+        if not self.live:
+            off = 0
+        else:
+            tail = self.live[0][1]
+            last = self.live[-1]
+            head = last[1] + last[2]
+            if last[1] >= tail:  # in use: [tail, head)
+                if head + n <= self.capacity:
+                    off = head
+                elif n <= tail:
+                    off = 0
+                else:
+                    return None
+            elif head + n <= tail:  # wrapped: in use [tail, capacity) and [0, head)
+                off = head
+            else:
+                return None
+        ent = [event, off, n, False]
+        self.live.append(ent)
+        self.where[event] = ent
+        return off
+
+    def offset(self, event):
+        return self.where[event][1]
+
+    def adjacent(self, a, b):
+        ea, eb = self.where.get(a), self.where.get(b)
+        return ea is not None and eb is not None and eb[1] == ea[1] + ea[2]
+
+    def release(self, event):
+        self.where.pop(event)[3] = True
+        while self.live and self.live[0][3]:
+            self.live.popleft()
+
+    def used_hits(self):
+        """Hits of the region held by live ranges and the gaps between them."""
+        if not self.live:
+            return 0
+        tail, last = self.live[0][1], self.live[-1]
+        head = last[1] + last[2]
+        return head - tail if last[1] >= tail else self.capacity - tail + head
 
 
 class Scheduler:
-    """Admission by HBM budget and continuous batching over backend slots."""
+    """Admission by HBM budget and continuous batching over backend slots.
+
+    A backend may provide ``admit(i, n_hits)`` (reserve device room for
+    event i and start its copy in; False while there is none), ``adjacent(i,
+    j)`` (events i and j sit back to back in device memory, so one batch can
+    take both) and ``release(events)`` (their room may be reused); without
+    them every event is admitted at once and consecutive events are adjacent."""
 
     def __init__(self, backend, *, hbm_budget_bytes=0, max_batch_hits, max_batch_events):
         self.backend = backend
@@ -112,6 +185,9 @@ class Scheduler:
                 raise ValueError(f"event {i} needs {fp} B, more than the HBM budget left for events")
             if n_hits[i] > self.max_batch_hits:
                 raise ValueError(f"event {i} has {n_hits[i]} hits, more than a slot holds ({self.max_batch_hits})")
+        admit = getattr(be, "admit", lambda i, n: True)
+        adjacent = getattr(be, "adjacent", lambda i, j: j == i + 1)
+        release = getattr(be, "release", lambda run: None)
         recs = [EventRecord(i, int(n_hits[i]), float(arrivals[i])) for i in range(N)]
         stats = RunStats(records=recs)
         queued = []        # arrived, not admitted (FIFO)
@@ -127,9 +203,13 @@ class Scheduler:
             while nxt < N and recs[nxt].t_arrival <= now:
                 queued.append(nxt)
                 nxt += 1
+            admitted_now = False
             while queued and (self.event_budget is None or
                               inflight + self.footprint(recs[queued[0]].n_hits) <= self.event_budget):
+                if not admit(queued[0], recs[queued[0]].n_hits):
+                    break  # no device room yet: the event waits for a completion
                 i = queued.pop(0)
+                admitted_now = True
                 recs[i].t_admit = now
                 inflight += self.footprint(recs[i].n_hits)
                 admitted.append(i)
@@ -139,7 +219,8 @@ class Scheduler:
                 run = [admitted[0]]
                 hits = recs[admitted[0]].n_hits
                 k = 1
-                while (k < len(admitted) and admitted[k] == run[-1] + 1 and len(run) < self.max_batch_events
+                while (k < len(admitted) and admitted[k] == run[-1] + 1 and adjacent(run[-1], admitted[k])
+                       and len(run) < self.max_batch_events
                        and hits + recs[admitted[k]].n_hits <= self.max_batch_hits):
                     run.append(admitted[k])
                     hits += recs[admitted[k]].n_hits
@@ -174,7 +255,8 @@ class Scheduler:
                     recs[i].t_done = t
                     inflight -= self.footprint(recs[i].n_hits)
                     done += 1
-            if not progressed and not (free and admitted) and not (queued and self.event_budget is None):
+                release(run)
+            if not progressed and not (free and admitted) and not admitted_now:
                 be.idle(recs[nxt].t_arrival if nxt < N else None, bool(busy))
         stats.wall_s = be.now() - t_start if t_start is not None else 0.0
         return stats
@@ -250,6 +332,148 @@ class GpuPoolBackend:
                 time.sleep(min(dt - 1e-4, 1e-3))
                 return
         time.sleep(2e-5)
+
+    def close(self):
+        for c in self.ctxs:
+            c.close()
+
+
+class GpuStagedBackend:
+    """Slots over the HIP library for events held in pinned host memory: the
+    host-resident served variant. Admitting event i reserves a contiguous range
+    of a device staging ring (inputs, event ids and outputs, POOL_BYTES_PER_HIT
+    per hit) and copies the event's inputs into it on a copy stream; a batch is
+    a run of events that sit back to back in the ring, clustered in place by
+    clue_run_batch_range once their copies are done. Outputs stay in device
+    memory; the ring range is reused after the batch completes. The ring holds
+    ``ring_hits`` hits, normally sized from the HBM budget left after the
+    slots' arenas, so admission gates real device memory.
+
+    ``host_events`` are the distinct events; arrival i carries event
+    ``i % len(host_events)``. Arrivals listed in ``keep`` also have their
+    outputs copied back to host memory after their batch, for checking."""
+
+    def __init__(self, params, host_events, *, ring_hits, slots=2, max_batch_hits, max_batch_events, tuning=None,
+                 flags=0, keep=()):
+        import torch
+
+        import paper_2001_09761_amd as clue
+        from .gen import concat_events
+        self.torch = torch
+        dev = torch.device("cuda", torch.cuda.current_device())
+        b = concat_events(host_events)
+        self.host = {k: torch.from_numpy(b[k]).pin_memory() for k in ("x", "y", "layer", "energy")}
+        self.host_offsets = np.concatenate([[0], np.cumsum([e["x"].size for e in host_events])]).astype(np.int64)
+        self.m = len(host_events)
+        self.ring = StagingRing(ring_hits)
+        C = int(ring_hits)
+        self.dev = {k: torch.empty(C, dtype=dt, device=dev) for k, dt in
+                    (("x", torch.float32), ("y", torch.float32), ("energy", torch.float32), ("layer", torch.int32),
+                     ("event", torch.int32), ("cluster_id", torch.int32), ("is_seed", torch.uint8))}
+        self.copy_stream = torch.cuda.Stream()  # default priority
+        self.ready = {}
+        self.n_hits = {}
+        self.keep = set(int(i) for i in keep)
+        self.kept = {}
+        self.n_slots = int(slots)
+        self.ctxs, self.streams = [], []
+        for _ in range(self.n_slots):
+            ctx = clue.Context(params["dc"], params["rho_c"], params["delta_c"], params["delta_o"],
+                               max_hits=max_batch_hits, max_events=max_batch_events,
+                               extent=params.get("extent"), bounds=params.get("bounds"),
+                               n_layers=params["n_layers"], flags=flags)
+            if tuning:
+                ctx.set_tuning(**tuning)
+            self.ctxs.append(ctx)
+            self.streams.append(torch.cuda.Stream())  # default priority
+        self._slot_bytes = clue.footprint_bytes(params["dc"], params["rho_c"], params["delta_c"], params["delta_o"],
+                                                max_batch_hits, max_batch_events, extent=params.get("extent"),
+                                                bounds=params.get("bounds"), n_layers=params["n_layers"],
+                                                flags=flags)
+        self.t0 = None
+
+    @staticmethod
+    def ring_hits_for(budget_bytes, slots, slot_bytes):
+        """Ring capacity that the HBM budget leaves after the slots' arenas."""
+        return max(0, (int(budget_bytes) - int(slots) * int(slot_bytes)) // POOL_BYTES_PER_HIT)
+
+    def staging_bytes(self):
+        return self.ring.capacity * POOL_BYTES_PER_HIT
+
+    def slot_bytes(self):
+        return self._slot_bytes
+
+    def _src(self, i):
+        k = i % self.m
+        return int(self.host_offsets[k]), int(self.host_offsets[k + 1])
+
+    def admit(self, i, n_hits):
+        a, b = self._src(i)
+        off = self.ring.allocate(i, b - a)
+        if off is None:
+            return False
+        d, h, n = self.dev, self.host, b - a
+        with self.torch.cuda.stream(self.copy_stream):
+            for k in ("x", "y", "layer", "energy"):
+                d[k][off:off + n].copy_(h[k][a:b], non_blocking=True)
+            d["event"][off:off + n].fill_(i)
+            ev = self.torch.cuda.Event()
+            ev.record(self.copy_stream)
+        self.ready[i] = ev
+        self.n_hits[i] = n
+        return True
+
+    def adjacent(self, i, j):
+        return self.ring.adjacent(i, j)
+
+    def release(self, run):
+        for i in run:
+            self.ring.release(i)
+            self.ready.pop(i, None)
+            self.n_hits.pop(i, None)
+
+    def start(self):
+        # admit, run and release arrival 0 on every slot before the clock
+        # starts (graph capture), then clear the ring
+        for slot in range(self.n_slots):
+            assert self.admit(0, None)
+            self.launch(slot, 0, 1)
+            self.torch.cuda.synchronize()
+            self.release([0])
+        self.kept.clear()
+        self.t0 = time.perf_counter()
+        return 0.0
+
+    def now(self):
+        return time.perf_counter() - self.t0
+
+    def launch(self, slot, first, count):
+        d = self.dev
+        off = self.ring.offset(first)
+        n = sum(self.n_hits[i] for i in range(first, first + count))
+        s = self.streams[slot]
+        s.wait_event(self.ready[first + count - 1])  # the copy stream is in order
+        z = off + n
+        self.ctxs[slot].run_batch_range(first, count, d["event"][off:z], d["x"][off:z], d["y"][off:z],
+                                        d["layer"][off:z], d["energy"][off:z], d["cluster_id"][off:z],
+                                        d["is_seed"][off:z], stream=s)
+        with self.torch.cuda.stream(s):
+            a = off
+            for i in range(first, first + count):
+                if i in self.keep:
+                    m = self.n_hits[i]
+                    self.kept[i] = (d["cluster_id"][a:a + m].to("cpu", non_blocking=True),
+                                    d["is_seed"][a:a + m].to("cpu", non_blocking=True))
+                a += self.n_hits[i]
+        ev = self.torch.cuda.Event()
+        ev.record(s)
+        return ev
+
+    def poll(self, slot, handle):
+        return "ok" if handle.query() else None
+
+    def idle(self, next_arrival, busy):
+        GpuPoolBackend.idle(self, next_arrival, busy)
 
     def close(self):
         for c in self.ctxs:

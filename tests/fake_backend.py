@@ -67,3 +67,33 @@ class FakeBackend:
             cands.append(next_arrival)
         if cands:
             self.t = max(self.t, min(cands))
+
+
+class FakeStagedBackend(FakeBackend):
+    """FakeBackend whose events must first be admitted into a staging ring of
+    ``ring_hits`` hits (the host-resident serving variant's bookkeeping):
+    admission fails while there is no contiguous room, a batch may only take
+    events that sit back to back in the ring, and completed events free their
+    range. Records the ring offset of every admission and the peak use."""
+
+    def __init__(self, events, params, *, ring_hits, **kw):
+        super().__init__(events, params, **kw)
+        from paper_2001_09761_amd.serve import StagingRing
+        self.ring = StagingRing(ring_hits)
+        self.offs = {}
+        self.peak_used = 0
+
+    def admit(self, i, n_hits):
+        off = self.ring.allocate(i, n_hits)
+        if off is None:
+            return False
+        self.offs[i] = off
+        self.peak_used = max(self.peak_used, self.ring.used_hits())
+        return True
+
+    def adjacent(self, i, j):
+        return self.ring.adjacent(i, j)
+
+    def release(self, run):
+        for i in run:
+            self.ring.release(i)

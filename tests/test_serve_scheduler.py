@@ -145,3 +145,56 @@ def test_plan_batch_takes_the_longest_fitting_prefix():
         k = plan_batch(sizes, cap_h, cap_e)
         assert 1 <= k <= min(cap_e, len(sizes)) and sum(sizes[:k]) <= cap_h
         assert k == min(cap_e, len(sizes)) or sum(sizes[:k + 1]) > cap_h
+
+
+def test_staging_ring_ranges_never_overlap():
+    """Random admissions and out-of-order releases: every live range lies in
+    the region, no two overlap, a range is freed for reuse only after all
+    older ones, and an empty ring always takes an event that fits."""
+    from paper_2001_09761_amd.serve import StagingRing
+    rng = np.random.default_rng(0)
+    for trial in range(40):
+        cap = int(rng.integers(50, 400))
+        ring = StagingRing(cap)
+        live = {}
+        nxt = 0
+        for _ in range(300):
+            if live and rng.random() < 0.45:
+                k = int(rng.choice(list(live)))
+                ring.release(k)
+                del live[k]
+            else:
+                n = int(rng.integers(1, cap // 2 + 1))
+                off = ring.allocate(nxt, n)
+                if not live:
+                    assert off == 0
+                if off is not None:
+                    assert 0 <= off and off + n <= cap
+                    live[nxt] = (off, n)
+                nxt += 1
+            held = sorted((e[1], e[1] + e[2]) for e in ring.live)
+            for (a0, a1), (b0, b1) in zip(held, held[1:]):
+                assert a1 <= b0, (trial, held)
+            assert ring.used_hits() <= cap
+    with pytest.raises(ValueError):
+        StagingRing(10).allocate(0, 11)
+
+
+def test_staged_admission_waits_for_room_and_batches_stay_contiguous():
+    """A staging ring that holds about two events: admission waits (the
+    budget binds), batches only take events adjacent in the ring, the ring
+    is never over-committed, and every result equals the event alone."""
+    evs = _events(12)
+    n_hits = [e["x"].size for e in evs]
+    from fake_backend import FakeStagedBackend
+    ring = 2 * max(n_hits) + 5
+    be = FakeStagedBackend(evs, P, ring_hits=ring, slots=2, service_time=lambda h: 3e-3)
+    st = Scheduler(be, max_batch_hits=10_000, max_batch_events=8).run(np.zeros(len(evs)), n_hits)
+    _check_results(be, evs)
+    _check_times(st)
+    s = st.summary()
+    assert s["admit_wait_p99_ms"] > 0 and be.peak_used <= ring
+    for slot, first, count, hits, *_ in st.batches:
+        for i in range(first, first + count - 1):
+            assert be.offs[i + 1] == be.offs[i] + n_hits[i]
+    assert sum(b[2] for b in st.batches) == len(evs)
