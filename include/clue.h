@@ -227,6 +227,40 @@ int clue_set_tuning(clue_ctx *c, const clue_tuning *t);
 /* Current tuning, and the staged halo width in tiles it implies. */
 int clue_get_tuning(const clue_ctx *c, clue_tuning *t, int32_t *halo);
 
+/* Bytes of device scratch the no-allocation form holds per device. */
+#define CLUE_NOALLOC_SCRATCH_BYTES (64ull << 20)
+
+/*
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc. Clusters one
+ * event exactly as clue_run does (same kernels, plain launches, identical
+ * results for the same parameters and tuning) with no context: its scratch
+ * arena is a fixed array of CLUE_NOALLOC_SCRATCH_BYTES in device memory that
+ * each device holds from the first call there until the process ends. The
+ * call allocates nothing, never synchronises and uses no memset node, so it
+ * may be captured into a graph.
+ *   p       parameters as for clue_create; CLUE_VALIDATE and
+ *           CLUE_KEEP_INTERMEDIATES are refused (they need a context).
+ *   t       tuning, or NULL for a fresh context's; fields <= 0 (and a
+ *           negative nh_first_radius) keep that default; plain_lds_cap,
+ *           when set, is the LDS cap used.
+ *   n, x, y, layer, energy, cluster_id, is_seed, stream: as for clue_run
+ *           (DEVICE pointers owned by the caller, on the calling thread's
+ *           current HIP device; n == 0 is a no-op).
+ * Limit: the arena for n hits (53 bytes per hit plus 4 bytes per grid tile,
+ * with the follower lists; about 1.2M hits on a 200 x 200 cm, 100-layer grid
+ * of 4 cm tiles) must fit the array, else CLUE_ERR_CAPACITY with no launch.
+ * Every call on one device shares that array and leaves its contents behind;
+ * each run clears what it reads first. Calls that overlap on one device (two
+ * streams, two threads) race on it and give undefined results: order them.
+ * Errors are returned synchronously (CLUE_ERR_ARG, CLUE_ERR_CAPACITY,
+ * CLUE_ERR_HIP); clue_last_error(NULL) gives the message of the calling
+ * thread's last failure.
+ */
+int clue_run_noalloc(const clue_params *p, const clue_tuning *t, int64_t n, const float *x, const float *y,
+                     const int32_t *layer, const float *energy, int32_t *cluster_id, uint8_t *is_seed,
+                     void *stream);
+
 /* Per-stage timing: when enabled, runs record HIP events between stages on
  * the run's stream (batched runs then launch the stage kernels directly
  * instead of through the graph, with identical kernels and launch shapes).

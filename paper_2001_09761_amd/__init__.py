@@ -18,7 +18,7 @@ from ._lib import (ClueError, KEEP_INTERMEDIATES, NO_FOLLOWERS, TIE_PAPER_STRICT
                    make_params)
 
 __all__ = ["Context", "Server", "ClueError", "VALIDATE", "KEEP_INTERMEDIATES", "TIE_PAPER_STRICT", "NO_FOLLOWERS",
-           "footprint_bytes"]
+           "footprint_bytes", "run_noalloc"]
 
 
 def _torch():
@@ -41,6 +41,36 @@ def footprint_bytes(dc, rho_c, delta_c, delta_o, max_hits, max_events=1, *, exte
     _lib.check(_lib.load().clue_footprint_bytes(ctypes.byref(p), int(max_hits), int(max_events),
                                                 ctypes.byref(out)))
     return int(out.value)
+
+
+def run_noalloc(dc, rho_c, delta_c, delta_o, x, y, layer, energy, cluster_id, is_seed, *, extent=None,
+                bounds=None, n_layers=100, tile_size=0.0, threads_per_query=0, flags=0, kernel="flat",
+                kernel_scale=0.0, tuning=None, stream=None):
+    """One event through ``clue_run_noalloc``: the plain form over the
+    library's fixed per-device scratch, for callers that cannot allocate.
+    The caller passes the outputs (``cluster_id`` int32, ``is_seed`` uint8);
+    ``tuning`` is a dict as returned by ``Context.tuning()`` or None."""
+    torch = _torch()
+    L = _lib.load()
+    p = make_params(dc, rho_c, delta_c, delta_o, _bounds(extent, bounds), n_layers, tile_size, threads_per_query,
+                    flags, kernel, kernel_scale)
+    t = None
+    if tuning is not None:
+        t = _lib.ClueTuning(float(tuning.get("tile_size", 0.0)), int(tuning.get("threads_per_query", 0)),
+                            int(tuning.get("block_x", 0)), int(tuning.get("block_y", 0)),
+                            int(tuning.get("lds_cap", 0)), float(tuning.get("nh_first_radius", -1.0)),
+                            int(tuning.get("density_quads", 0)), int(tuning.get("plain_lds_cap", 0)),
+                            int(tuning.get("expansion", 0)))
+    n = int(x.numel())
+    dev = Context._dev
+    s = torch.cuda.current_stream() if stream is None else stream
+    rc = L.clue_run_noalloc(ctypes.byref(p), ctypes.byref(t) if t is not None else None, n,
+                            dev(None, x, torch.float32, "x", n), dev(None, y, torch.float32, "y", n),
+                            dev(None, layer, torch.int32, "layer", n), dev(None, energy, torch.float32, "energy", n),
+                            dev(None, cluster_id, torch.int32, "cluster_id", n),
+                            dev(None, is_seed, torch.uint8, "is_seed", n), ctypes.c_void_p(s.cuda_stream))
+    _lib.check(rc, None)
+    return cluster_id, is_seed
 
 
 class Context:

@@ -18,6 +18,7 @@ CLUE_OK = 0
 ERRORS = {-1: "CLUE_ERR_ARG", -2: "CLUE_ERR_CAPACITY", -3: "CLUE_ERR_NOMEM", -4: "CLUE_ERR_HIP",
           -5: "CLUE_ERR_INPUT", -6: "CLUE_ERR_BUDGET", -7: "CLUE_ERR_STATE", -8: "CLUE_ERR_DEVICE"}
 VALIDATE, KEEP_INTERMEDIATES, TIE_PAPER_STRICT, NO_FOLLOWERS = 1, 2, 4, 8
+NOALLOC_SCRATCH_BYTES = 64 << 20  # CLUE_NOALLOC_SCRATCH_BYTES
 
 
 class ClueParams(ctypes.Structure):
@@ -88,6 +89,8 @@ def load(path: str = LIB_PATH):
         "clue_get_tuning": ([P, ctypes.POINTER(ClueTuning), ctypes.POINTER(i32)], ctypes.c_int),
         "clue_enable_stage_timing": ([P, ctypes.c_int], ctypes.c_int),
         "clue_stage_times": ([P, ctypes.POINTER(f32), ctypes.POINTER(ctypes.c_char_p), ctypes.c_int], ctypes.c_int),
+        "clue_run_noalloc": ([ctypes.POINTER(ClueParams), ctypes.POINTER(ClueTuning), i64, P, P, P, P, P, P, P],
+                             ctypes.c_int),
         "clue_last_error": ([P], ctypes.c_char_p),
         "clue_destroy": ([P], None),
     }

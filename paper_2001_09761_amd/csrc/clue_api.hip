@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -238,11 +239,11 @@ static bool plan_arena(const Geom& g, int64_t N, int32_t E, ArenaPlan& P) {
   return true;
 }
 
-static void bind_arena(clue_ctx* c, const ArenaPlan& P, int64_t N, int32_t E) {
-  char* b = (char*)c->arena_base;
-  Arena& a = c->a;
-  const bool fol = builds_lists(c->g);
-  const bool keep = c->params.flags & CLUE_KEEP_INTERMEDIATES;
+// Sub-buffers of an arena that starts at `b`, laid out by `P`.
+static Arena arena_at(char* b, const Geom& g, const ArenaPlan& P, int64_t N, int32_t E) {
+  Arena a{};
+  const bool fol = builds_lists(g);
+  const bool keep = g.flags & CLUE_KEEP_INTERMEDIATES;
   a.key = (int32_t*)(b + P.off[A_KEY]);
   a.rank = (int32_t*)(b + P.off[A_RANK]);
   a.tile_start = (int32_t*)(b + P.off[A_TS]);
@@ -269,6 +270,11 @@ static void bind_arena(clue_ctx* c, const ArenaPlan& P, int64_t N, int32_t E) {
   a.cap_events = E;
   a.cap_tiles = P.tiles;
   a.cap_chunks = P.chunks;
+  return a;
+}
+
+static void bind_arena(clue_ctx* c, const ArenaPlan& P, int64_t N, int32_t E) {
+  c->a = arena_at((char*)c->arena_base, c->g, P, N, E);
 }
 
 static void drop_graph(clue_ctx* c) {
@@ -795,6 +801,115 @@ int clue_stage_times(clue_ctx* c, float* ms, const char** names, int cap) {
     if (names) names[k] = kStageNames[k];
   }
   return S_COUNT;
+}
+
+// ---------------------------------------------------------------------------
+// The no-allocation form: the plain one-event pipeline over a fixed scratch
+// array in device memory. The array is a module global, so each device that
+// loads this library holds its own copy until the process ends; its device
+// address is looked up once per device (the name itself is only a host-side
+// stand-in) and every run on that device shares it.
+// ---------------------------------------------------------------------------
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;  // CLUE_NOALLOC_SCRATCH_BYTES
+static_assert(kNoAllocScratchBytes == (size_t)CLUE_NOALLOC_SCRATCH_BYTES, "header and library agree on the size");
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Device address of `scratch` on the current device `dev`, looked up on the
+// first call there.
+static int scratch_on_device(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxScratchDevices)
+    return set_err(nullptr, CLUE_ERR_ARG, "device index beyond the no-allocation form's table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return set_err(nullptr, CLUE_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return CLUE_OK;
+}
+
+int clue_run_noalloc(const clue_params* p, const clue_tuning* t, int64_t n, const float* x, const float* y,
+                     const int32_t* layer, const float* energy, int32_t* cluster_id, uint8_t* is_seed,
+                     void* stream) {
+  if (!p) return set_err(nullptr, CLUE_ERR_ARG, "null params");
+  if (n < 0 || n >= ((int64_t)1 << 31) - 1) return set_err(nullptr, CLUE_ERR_ARG, "n out of range");
+  if (n > 0 && (!x || !y || !layer || !energy || !cluster_id || !is_seed))
+    return set_err(nullptr, CLUE_ERR_ARG, "null input or output pointer");
+  if (p->flags & (CLUE_VALIDATE | CLUE_KEEP_INTERMEDIATES))
+    return set_err(nullptr, CLUE_ERR_ARG,
+                   "CLUE_VALIDATE and CLUE_KEEP_INTERMEDIATES need a context: the no-allocation form "
+                   "neither synchronises nor keeps results past the call");
+  // the tuning of a fresh context, with any positive field of *t in its place
+  const clue_ctx defaults{};
+  float tile = p->tile_size;
+  int tpq = p->threads_per_query > 0 ? p->threads_per_query : 1;
+  int bx = defaults.bx, by = defaults.by, cap = defaults.lds_cap, quads = defaults.quads;
+  float r1 = defaults.r1;
+  int expansion = defaults.expansion;
+  if (t) {
+    if (t->tile_size > 0.0f) tile = t->tile_size;
+    if (t->threads_per_query > 0) tpq = t->threads_per_query;
+    if (t->block_x > 0) bx = t->block_x;
+    if (t->block_y > 0) by = t->block_y;
+    // a single event runs as the plain form: its own cap when set
+    if (t->plain_lds_cap > 0)
+      cap = t->plain_lds_cap;
+    else if (t->lds_cap > 0)
+      cap = t->lds_cap;
+    if (t->nh_first_radius >= 0.0f) r1 = t->nh_first_radius;
+    if (t->density_quads > 0) quads = t->density_quads;
+    if (t->expansion > 0) expansion = t->expansion;
+  }
+  Geom g{};
+  std::string msg;
+  int rc = plan_geom(*p, tile, tpq, bx, by, cap, r1, quads, expansion, g, msg);
+  if (rc != CLUE_OK) return set_err(nullptr, rc, msg);
+  ArenaPlan P;
+  if (!plan_arena(g, std::max<int64_t>(n, 1), 1, P) || P.total > kNoAllocScratchBytes)
+    return set_err(nullptr, CLUE_ERR_CAPACITY,
+                   "the no-allocation form holds " + std::to_string(kNoAllocScratchBytes) +
+                       " bytes of scratch per device; this run of " + std::to_string(n) + " hits needs " +
+                       std::to_string(P.total) + " (use a context)");
+  if (n == 0) return CLUE_OK;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return set_err(nullptr, CLUE_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  void* base = nullptr;
+  rc = scratch_on_device(dev, &base);
+  if (rc != CLUE_OK) return rc;
+  const Arena a = arena_at((char*)base, g, P, n, 1);
+  RunDesc d{};
+  d.n = (int32_t)n;
+  d.n_events = 1;
+  d.x = x;
+  d.y = y;
+  d.e = energy;
+  d.layer = layer;
+  d.event = nullptr;
+  d.event_base = 0;
+  d.cluster_id = cluster_id;
+  d.is_seed = is_seed;
+  // plain launches, sized to the run; the first kernel clears every counter,
+  // tile count and scan status the run reads, so the previous call's
+  // contents do not matter
+  LaunchCfg cfg{};
+  cfg.graph_mode = false;
+  if (g.expand) {  // the k-way walk's grid: one run of workgroups per XCD
+    int ncu = 0;
+    e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return set_err(nullptr, CLUE_ERR_HIP, std::string("hipDeviceGetAttribute: ") + hipGetErrorString(e));
+    cfg.persist_blocks_stream = std::max(1, ncu) * 8;
+  }
+  e = launch_pipeline(g, a, d, cfg, (hipStream_t)stream, nullptr);
+  if (e != hipSuccess) return set_err(nullptr, CLUE_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+  return CLUE_OK;
 }
 
 const char* clue_last_error(const clue_ctx* c) {
