@@ -90,6 +90,121 @@ def cpu_baseline(events, params, budget_s=12.0):
             "cpu_model": model}
 
 
+def host_cores():
+    return len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+
+
+def oracle_median_s(ev, params, threads, reps=5):
+    """Median wall time (s) of `reps` oracle runs on one event (input
+    generation excluded), the oracle's outputs of the last run."""
+    import numpy as np
+    import oracle
+    ts, out = [], None
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        out = oracle.run_event(ev, params, n_threads=threads, want=("rho", "rho64"))
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts)), out
+
+
+def linear_fit(xs, ys):
+    import numpy as np
+    x, y = np.asarray(xs, float), np.asarray(ys, float)
+    a, b = np.polyfit(x, y, 1)
+    r = np.corrcoef(x, y)[0, 1]
+    return {"slope_ms_per_Mhit": round(a * 1e6, 5), "intercept_ms": round(b, 5), "r2": round(float(r * r), 5)}
+
+
+def config_runs(log, with_cpu):
+    """Configs 1 and 3 and the single 1M-hit event of config 2, each as one
+    event through the plain form (per-stage launches) and the batched form
+    (one graph), device-timed with HIP events on the stream (p50 / p99 over 100
+    runs for config 1, median of 20 otherwise), compared bit for bit with the
+    oracle; the GPU density's largest relative error against the oracle's
+    binary64 sum of the same neighbours; and, with `with_cpu`, the oracle's
+    median of 5 runs on 1 thread and on all host cores."""
+    import numpy as np
+    import torch
+
+    import paper_2001_09761_amd as clue
+    from paper_2001_09761_amd import gen
+
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream()
+    cores = host_cores()
+
+    def one(ev, p, reps, name, cpu_1t=True):
+        n = int(ev["x"].size)
+        t = {k: torch.from_numpy(v).to(dev) for k, v in ev.items() if isinstance(v, np.ndarray)}
+        ev_ids = torch.zeros(n, dtype=torch.int32, device=dev)
+        cid = torch.empty(n, dtype=torch.int32, device=dev)
+        seed = torch.empty(n, dtype=torch.uint8, device=dev)
+        row = {"hits": n}
+        with clue.Context(p["dc"], p["rho_c"], p["delta_c"], p["delta_o"], max_hits=n, extent=p["extent"],
+                          n_layers=p["n_layers"], flags=clue.KEEP_INTERMEDIATES) as ctx:
+            for form, fn in (("plain", lambda: ctx.run(t["x"], t["y"], t["layer"], t["energy"], cid, seed)),
+                             ("batched", lambda: ctx.run_batch(ev_ids, 1, t["x"], t["y"], t["layer"], t["energy"],
+                                                               cid, seed))):
+                for _ in range(3):
+                    fn()
+                ms = []
+                for _ in range(reps):
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    fn()
+                    e1.record(stream)
+                    e1.synchronize()
+                    ms.append(e0.elapsed_time(e1))
+                row[f"{form}_ms_p50"] = round(percentile(ms, 50), 4)
+                row[f"{form}_ms_p99"] = round(percentile(ms, 99), 4)
+                row[f"{form}_hits_per_s"] = round(n / percentile(ms, 50) * 1e3, 1)
+            rho = ctx.intermediates()["rho"].cpu().numpy()
+            torch.cuda.synchronize()
+            ctx.status()
+            got_cid, got_seed = cid.cpu().numpy(), seed.cpu().numpy()
+        import oracle
+        ref = oracle.run_event(ev, p, n_threads=cores, want=("rho", "rho64"))
+        row["bit_exact_vs_oracle"] = bool(np.array_equal(got_cid, ref["cluster_id"]) and
+                                          np.array_equal(got_seed, ref["is_seed"]) and
+                                          np.array_equal(rho.view(np.uint32), ref["rho"].view(np.uint32)))
+        rel = np.abs(rho.astype(np.float64) - ref["rho64"]) / np.maximum(np.abs(ref["rho64"]), 1e-30)
+        row["rho_fp64_max_rel_err"] = float(rel.max()) if n else 0.0
+        if with_cpu:
+            t_all, _ = oracle_median_s(ev, p, cores)
+            row["oracle_all_cores_ms"] = round(t_all * 1e3, 3)
+            row["oracle_all_cores_hits_per_s"] = round(n / t_all, 1)
+            if cpu_1t:
+                t_one, _ = oracle_median_s(ev, p, 1)
+                row["oracle_1_thread_ms"] = round(t_one * 1e3, 3)
+                row["oracle_1_thread_hits_per_s"] = round(n / t_one, 1)
+        log(f"{name}: plain {row['plain_ms_p50']} ms, batched {row['batched_ms_p50']} ms, "
+            f"bit-exact {row['bit_exact_vs_oracle']}")
+        return row
+
+    out = {"cpu": {"cores": cores, "reps": 5, "statistic": "median"} if with_cpu else None}
+    ev, p = gen.config1()
+    out["config1"] = {"workload": "1 layer, 1,000 hits, 100x100 cm, 50 clusters x 19 + 50 noise", **one(ev, p, 100, "config 1")}
+    ev, p = gen.config2()
+    out["config2_event"] = {"workload": "one 1M-hit event (100 layers x 10k hits)", **one(ev, p, 20, "config 2")}
+    sweep = []
+    for step in range(1, 11):
+        ev, p = gen.config3_sweep(step)
+        # the single-thread oracle at three points of the sweep (it takes ~1.4 s per 1M hits)
+        sweep.append({"hits_per_layer": 1000 * step, **one(ev, p, 20, f"config 3 step {step}",
+                                                             cpu_1t=step in (1, 5, 10))})
+    fit = {form: linear_fit([r["hits"] for r in sweep], [r[f"{form}_ms_p50"] for r in sweep])
+           for form in ("plain", "batched")}
+    out["config3_sweep"] = {"workload": "100 layers x 1k..10k hits per layer (0.1M..1M hits), 5% noise, "
+                                        "Gaussian clusters of 20", "rows": sweep, "linear_fit_ms_vs_hits": fit}
+    hard = []
+    for dc in (1.0, 2.0, 3.0):
+        ev, p = gen.config3_hard(dc)
+        hard.append({"dc": dc, **one(ev, p, 20, f"config 3 hard dc={dc:g}")})
+    out["config3_hard"] = {"workload": "100 layers x 10k hits, 20% noise, rings and crescents", "rows": hard}
+    return out
+
+
 def tuning_kwargs(t):
     """A tuner result as Context.set_tuning keyword arguments."""
     kw = {k: v for k, v in t.items() if k in ("tile_size", "threads_per_query", "lds_cap", "nh_first_radius",
@@ -122,7 +237,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-extras", action="store_true", help="headline only (no 64-event or served runs)")
     ap.add_argument("--serve-rate", type=float, default=2000.0, help="offered events/s of the served stream")
-    ap.add_argument("--no-sweep", action="store_true", help="skip the served-rate sweep (100 to 5000 events/s)")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the served-rate sweeps")
+    ap.add_argument("--serve-events", type=int, default=2000, help="Poisson arrivals per served rate (>= 2000)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB device copy (HBM counter calibration)")
     ap.add_argument("--traffic-summary", metavar="DIR",
@@ -207,7 +323,7 @@ def main():
 
     # ---- per-step times (HIP events around each step), median and p99 -------
     step_ms = []
-    for _ in range(max(20, args.steps)):
+    for _ in range(max(100, args.steps)):
         s0 = torch.cuda.Event(enable_timing=True)
         s1 = torch.cuda.Event(enable_timing=True)
         s0.record(stream)
@@ -240,7 +356,7 @@ def main():
     # ---- single-event latency (plain form, device time) ------------------
     lat_plain = []
     a, b = int(offs[0]), int(offs[1])
-    for _ in range(40):
+    for _ in range(110):
         s0 = torch.cuda.Event(enable_timing=True)
         s1 = torch.cuda.Event(enable_timing=True)
         s0.record(stream)
@@ -248,7 +364,7 @@ def main():
         s1.record(stream)
         s1.synchronize()
         lat_plain.append(s0.elapsed_time(s1))
-    lat_plain = lat_plain[5:]
+    lat_plain = lat_plain[10:]
 
     # ---- per-stage times of the batched kernels (HIP events on the stream) -
     ctx.enable_stage_timing(True)
@@ -352,6 +468,11 @@ def main():
         out["expansion"] = expansion
 
     if not args.no_extras:
+        out["configs"] = config_runs(log, not args.no_cpu)
+        errs = [out["configs"]["config1"]["rho_fp64_max_rel_err"], out["configs"]["config2_event"]["rho_fp64_max_rel_err"]]
+        errs += [r["rho_fp64_max_rel_err"] for r in out["configs"]["config3_sweep"]["rows"]]
+        errs += [r["rho_fp64_max_rel_err"] for r in out["configs"]["config3_hard"]["rows"]]
+        out["rho_fp64_max_rel_err"] = max(errs)
         out["host_resident"] = host_resident(events, params, log)
         out.update(extras(args, params, log))
         out["paper_workload"] = paper_workload(log)
@@ -573,6 +694,24 @@ def host_resident(events, params, log):
     return out
 
 
+def replicated_pool(batch, reps, dev):
+    """A device event pool of `reps` copies of a host batch of events: inputs,
+    pool event ids (copy r of event e is pool event r * E + e) and outputs."""
+    import numpy as np
+    import torch
+    E = int(batch["n_events"])
+    sizes = np.bincount(batch["event"], minlength=E).astype(np.int64)
+    pool = {k: torch.from_numpy(batch[k]).to(dev).repeat(reps) for k in ("x", "y", "layer", "energy")}
+    counts = torch.from_numpy(np.tile(sizes, reps)).to(dev)
+    n = int(counts.sum().item())
+    pool["event"] = torch.repeat_interleave(torch.arange(E * reps, dtype=torch.int32, device=dev), counts,
+                                            output_size=n)
+    pool["cluster_id"] = torch.empty(n, dtype=torch.int32, device=dev)
+    pool["is_seed"] = torch.empty(n, dtype=torch.uint8, device=dev)
+    pool["offsets"] = np.concatenate([[0], np.cumsum(np.tile(sizes, reps))]).astype(np.int64)
+    return pool
+
+
 def extras(args, params, log):
     """64-event batch (plain vs batched) and a served Poisson stream."""
     import numpy as np
@@ -580,7 +719,7 @@ def extras(args, params, log):
 
     import paper_2001_09761_amd as clue
     from paper_2001_09761_amd import gen
-    from paper_2001_09761_amd.serve import GpuPoolBackend, Scheduler, make_pool
+    from paper_2001_09761_amd.serve import POOL_BYTES_PER_HIT, GpuPoolBackend, Scheduler
 
     dev = torch.device("cuda", 0)
     res = {}
@@ -619,42 +758,103 @@ def extras(args, params, log):
                       "batched_over_plain": round(tb[1] / tb[0], 3), "tuning": tuning}
     del d
 
-    # served stream: Poisson arrivals of such events, pool of 64 distinct events x4
-    pool_events = evs * 4
-    pool = make_pool(pool_events, dev)
-    n_hits = [e["x"].size for e in pool_events]
+    # served stream (config 5): Poisson arrivals of such events over a
+    # device-resident pool, the 64 distinct events replicated to 2048 entries,
+    # and at least 2000 arrivals per offered rate; every served event's labels
+    # are checked against the oracle's after each rate
+    import oracle
+    reps = 32
+    n_arr = max(2000, args.serve_events)
+    ref = oracle.run(b["x"], b["y"], b["layer"], b["energy"], event=b["event"], n_events=64,
+                     n_threads=host_cores(), want=(), dc=params["dc"], rho_c=params["rho_c"],
+                     delta_c=params["delta_c"], delta_o=params["delta_o"], extent=200.0, n_layers=100)
+    pool = replicated_pool(b, reps, dev)
+    ref_cid = torch.from_numpy(ref["cluster_id"]).to(dev).repeat(reps)
+    ref_seed = torch.from_numpy(ref["is_seed"]).to(dev).repeat(reps)
+    n_hits = np.diff(pool["offsets"]).tolist()
     cap = 8 * max(n_hits)
     be = GpuPoolBackend(params, pool, slots=2, max_batch_hits=cap, max_batch_events=8,
                         tuning=tuning_kwargs(tuning))
+    checked = {"events": 0, "bit_exact": True}
+
     def served(rate):
-        arrivals = gen.poisson_arrivals(rate, len(pool_events))
+        pool["cluster_id"].fill_(-7)
+        pool["is_seed"].fill_(7)
+        arrivals = gen.poisson_arrivals(rate, n_arr)
         sch = Scheduler(be, hbm_budget_bytes=64 << 30, max_batch_hits=cap, max_batch_events=8)
-        return sch.run(arrivals, n_hits).summary()
+        summ = sch.run(arrivals, n_hits[:n_arr]).summary()
+        torch.cuda.synchronize()
+        z = int(pool["offsets"][n_arr])
+        ok = bool(torch.equal(pool["cluster_id"][:z], ref_cid[:z]) and torch.equal(pool["is_seed"][:z], ref_seed[:z]))
+        checked["events"] += n_arr
+        checked["bit_exact"] &= ok
+        return summ
 
     s = served(args.serve_rate)
-    res["serving"] = {"workload": "Poisson stream of 100-layer x U[1000,10000]-hit events, device-resident pool",
+    res["serving"] = {"workload": "Poisson stream of 100-layer x U[1000,10000]-hit events, device-resident pool "
+                                  "(64 distinct events x 32)", "arrivals": n_arr,
                       "offered_events_per_s": args.serve_rate, "slots": 2, "hbm_budget_bytes": 64 << 30,
                       **{k: (round(v, 4) if isinstance(v, float) else v) for k, v in s.items()}}
     if not args.no_sweep:
         sweep = []
-        for rate in (100.0, 250.0, 500.0, 1000.0, 2000.0, 5000.0):
+        for rate in (100.0, 250.0, 500.0, 1000.0, 2000.0, 5000.0, 10000.0, 20000.0):
             s = served(rate)
             sweep.append({"offered_events_per_s": rate, "events": s["events"],
                           "events_per_s": round(s["events_per_s"], 1), "hits_per_s": round(s["hits_per_s"], 1),
                           "p50_ms": round(s["p50_ms"], 4), "p99_ms": round(s["p99_ms"], 4),
                           "mean_batch_events": round(s["mean_batch_events"], 3)})
-            log(f"served {rate:g}/s: p50 {s['p50_ms']:.3f} ms p99 {s['p99_ms']:.3f} ms")
+            log(f"served {rate:g}/s: p50 {s['p50_ms']:.3f} ms p99 {s['p99_ms']:.3f} ms, "
+                f"{s['mean_batch_events']:.2f} events per batch")
         res["serving_sweep"] = sweep
+    res["served_verified"] = checked
     be.close()
+    del pool, ref_cid, ref_seed
+
+    # host-resident served variant: events in pinned host memory, admitted into
+    # a device staging ring sized from an HBM budget that holds the two slots'
+    # arenas plus about four events; the budget binds, so events wait for room
+    if not args.no_sweep:
+        from paper_2001_09761_amd.serve import GpuStagedBackend
+        slot_bytes = clue.footprint_bytes(params["dc"], params["rho_c"], params["delta_c"], params["delta_o"], cap, 8,
+                                          extent=200.0, n_layers=100)
+        budget = 2 * slot_bytes + 4 * max(n_hits[:64]) * POOL_BYTES_PER_HIT
+        ring = GpuStagedBackend.ring_hits_for(budget, 2, slot_bytes)
+        keep = list(range(0, n_arr, 50))
+        staged = []
+        for rate in (1000.0, 2000.0, 5000.0):
+            sb = GpuStagedBackend(params, evs, ring_hits=ring, slots=2, max_batch_hits=cap, max_batch_events=8,
+                                  tuning=tuning_kwargs(tuning), keep=keep)
+            st = Scheduler(sb, hbm_budget_bytes=budget, max_batch_hits=cap, max_batch_events=8).run(
+                gen.poisson_arrivals(rate, n_arr), [int(np.diff(sb.host_offsets)[i % 64]) for i in range(n_arr)])
+            torch.cuda.synchronize()
+            ok = all(np.array_equal(sb.kept[i][0].numpy(), ref["cluster_id"][int(offs[i % 64]):int(offs[i % 64 + 1])])
+                     and np.array_equal(sb.kept[i][1].numpy(), ref["is_seed"][int(offs[i % 64]):int(offs[i % 64 + 1])])
+                     for i in keep)
+            sm = st.summary()
+            staged.append({"offered_events_per_s": rate, "events": sm["events"],
+                           "events_per_s": round(sm["events_per_s"], 1), "hits_per_s": round(sm["hits_per_s"], 1),
+                           "p50_ms": round(sm["p50_ms"], 4), "p99_ms": round(sm["p99_ms"], 4),
+                           "admit_wait_p50_ms": round(sm["admit_wait_p50_ms"], 4),
+                           "admit_wait_p99_ms": round(sm["admit_wait_p99_ms"], 4),
+                           "mean_batch_events": round(sm["mean_batch_events"], 3),
+                           "max_inflight_bytes": sm["max_inflight_bytes"],
+                           "verified_events": len(keep), "bit_exact": ok})
+            log(f"staged served {rate:g}/s: p50 {sm['p50_ms']:.3f} ms p99 {sm['p99_ms']:.3f} ms, admission wait "
+                f"p99 {sm['admit_wait_p99_ms']:.3f} ms")
+            sb.close()
+            del sb
+        res["serving_host_staged"] = {
+            "workload": "the same Poisson stream from pinned host memory; each admitted event is copied into a "
+                        "device staging ring (inputs, ids, outputs: 25 B per hit) sized from the HBM budget",
+            "hbm_budget_bytes": int(budget), "staging_ring_hits": int(ring), "slots": 2, "rows": staged}
 
     # online form: the same events submitted as device tensors in one burst;
     # each future's latency runs from its submit to its completion callback
     srv_tuning = tuning_kwargs(tuning)
     with clue.Server(params["dc"], params["rho_c"], params["delta_c"], params["delta_o"], max_batch_hits=cap,
                      max_batch_events=8, slots=2, extent=200.0, n_layers=100, tuning=srv_tuning) as srv:
-        offs_p = pool["offsets"]
-        views = [(pool["x"][int(offs_p[i]):int(offs_p[i + 1])], pool["y"][int(offs_p[i]):int(offs_p[i + 1])],
-                  pool["layer"][int(offs_p[i]):int(offs_p[i + 1])], pool["energy"][int(offs_p[i]):int(offs_p[i + 1])])
+        dv = {k: torch.from_numpy(b[k]).to(dev) for k in ("x", "y", "layer", "energy")}
+        views = [tuple(dv[k][int(offs[i]):int(offs[i + 1])] for k in ("x", "y", "layer", "energy"))
                  for i in range(len(evs))]
         for f in [srv.submit(*v) for v in views]:  # warm-up burst: graphs captured, memory cached
             f.result()
