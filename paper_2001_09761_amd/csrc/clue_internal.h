@@ -118,7 +118,8 @@ struct Arena {
   float* rho;            // [N]   slot order
   int32_t* parent;       // [N]   slot order: nearest-higher slot of a follower, else itself
   uint8_t* flags;        // [N]   slot order: F_SEED | F_OUTLIER | F_FOLLOWER
-  int32_t* seed_rank;    // [N+1] caller order: exclusive count of seeds
+  uint32_t* seedbits;    // [N/32+2] caller order: one bit per hit, set for seeds
+  int32_t* seed_wrank;   // [N/32+2] seeds in the words before each word of seedbits
   int32_t* ev_start;     // [E+1] caller-order first hit of each event
   int32_t* fstart;       // [N+1] caller order: follower counts, scanned into CSR offsets
   int32_t* frank;        // [N]   slot order: rank of a follower within its owner's list

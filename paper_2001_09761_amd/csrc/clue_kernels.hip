@@ -11,7 +11,8 @@
 //                      lists of the index-ordered tiles
 //   k_nearest_higher   nh / delta (Eq. 4, Algorithm 2) fused with the seed /
 //                      outlier / follower decision (Sec. 2.2, Algorithm 3)
-//   k_scan<SEEDS>      seed numbering by prefix scan (and follower list offsets)
+//   k_scan<SEEDS>      seed numbering by prefix scan over the seed bitmap (and
+//                      follower list offsets); writes the caller-order seed flags
 //   k_label            cluster ids: each hit follows nearest-higher links of
 //                      followers to its root (pointer jumping with path
 //                      compression); registers follower-list entries
@@ -91,6 +92,15 @@ __device__ __forceinline__ int event_first_hit(const Arena& a, const RunDesc& d,
   return clampi(a.ev_start[e], 0, d.n);
 }
 
+// Seeds are marked by one bit per hit in caller order; the seed scan gives
+// the count before each 32-bit word. Words cover hits 0..n, so the rank of
+// n (the seed total) is defined too.
+__host__ __device__ __forceinline__ int64_t seed_words(int64_t n) { return n / 32 + 1; }
+// Seeds among caller hits 0..h-1 (h in [0, n]).
+__device__ __forceinline__ int seed_rank(const Arena& a, int h) {
+  return a.seed_wrank[h >> 5] + __popc(a.seedbits[h >> 5] & ((1u << (h & 31)) - 1u));
+}
+
 // ---------------------------------------------------------------------------
 // Streaming kernels cut their index range into chunks of `chunk` consecutive
 // indices and give each XCD one contiguous run of chunks (workgroups are
@@ -129,6 +139,7 @@ __global__ __launch_bounds__(kWG) void k_clear(DescArg<G> dg, Geom g, Arena a) {
   for (int64_t i = i0; i < nchunk_s && i < a.cap_chunks; i += stride) a.scan_status[a.cap_chunks + i] = 0ull;
   for (int64_t i = i0; i < C_COUNT; i += stride) a.counters[i] = 0;
   for (int64_t i = i0; i <= d.n_events; i += stride) a.ev_start[i] = 0;
+  for (int64_t i = i0; i < seed_words(d.n); i += stride) a.seedbits[i] = 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -354,20 +365,32 @@ __global__ __launch_bounds__(kWG) void k_scan(DescArg<G> dg, Geom g, Arena a) {
         for (int i = 0; i < SI; ++i) v[0][i] = base + i < nel ? a.tile_start[base + i] : 0;
       }
     } else {
-      const bool aligned = ((uintptr_t)d.is_seed & 15u) == 0;
-      if (aligned && base + SI <= nel) {
-        static_assert(SI % 16 == 0, "the seed flags load in 16-byte words");
-        unsigned ww[SI / 4];
+      // channel 0: the seeds of bitmap word w at element 32 w, zero elsewhere,
+      // so that the prefix at 32 w counts the seeds before word w
+      static_assert(SI % 32 == 0 || 32 % SI == 0, "a thread's elements hold whole words or none");
+      const int64_t nw = seed_words(d.n);
 #pragma unroll
-        for (int q = 0; q < SI / 16; ++q) {
-          const uint4 w = reinterpret_cast<const uint4*>(d.is_seed + base)[q];
-          ww[4 * q] = w.x; ww[4 * q + 1] = w.y; ww[4 * q + 2] = w.z; ww[4 * q + 3] = w.w;
+      for (int i = 0; i < SI; ++i) {
+        const int64_t e = base + i;
+        v[0][i] = ((e & 31) == 0 && (e >> 5) < nw) ? __popc(a.seedbits[e >> 5]) : 0;
+      }
+      // the caller-order seed flags, expanded from the bitmap 16 at a time
+      // (one bit per hit -> one byte per hit), in coalesced stores
+      static_assert(SI % 16 == 0, "flags are written 16 at a time");
+#pragma unroll
+      for (int q = 0; q < SI; q += 16) {
+        const int64_t e0 = base + q;
+        if (e0 >= nel) break;
+        const unsigned w = (a.seedbits[e0 >> 5] >> (e0 & 31)) & 0xffffu;
+        unsigned b4[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) b4[k] = (((w >> (4 * k)) & 0xfu) * 0x00204081u) & 0x01010101u;
+        uint8_t* dst = d.is_seed + e0;
+        if (e0 + 16 <= nel && ((uintptr_t)dst & 15u) == 0) {
+          *reinterpret_cast<uint4*>(dst) = make_uint4(b4[0], b4[1], b4[2], b4[3]);
+        } else {
+          for (int k = 0; k < 16 && e0 + k < nel; ++k) dst[k] = (uint8_t)((w >> k) & 1u);
         }
-#pragma unroll
-        for (int i = 0; i < SI; ++i) v[0][i] = (ww[i >> 2] >> (8 * (i & 3))) & 0xffu ? 1 : 0;
-      } else {
-#pragma unroll
-        for (int i = 0; i < SI; ++i) v[0][i] = base + i < nel ? (d.is_seed[base + i] ? 1 : 0) : 0;
       }
       if constexpr (NCH == 2) {
         if (base + SI <= nel) {
@@ -462,7 +485,13 @@ __global__ __launch_bounds__(kWG) void k_scan(DescArg<G> dg, Geom g, Arena a) {
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
       const int off = s_prefix[c] + wbase[c] + texcl[c];
-      int* out = KIND == SCAN_TILES ? a.tile_start : (c == 0 ? a.seed_rank : a.fstart);
+      if (KIND != SCAN_TILES && c == 0) {  // one count per bitmap word
+#pragma unroll
+        for (int i = 0; i < SI; i += 32)
+          if (base + i < nout && ((base + i) & 31) == 0) a.seed_wrank[(base + i) >> 5] = off + v[c][i];
+        continue;
+      }
+      int* out = KIND == SCAN_TILES ? a.tile_start : a.fstart;
       if (base + SI <= nout) {
         int4* p = reinterpret_cast<int4*>(out + base);
 #pragma unroll
@@ -878,33 +907,44 @@ __device__ __forceinline__ float density_two_pass(const float4* __restrict__ rec
   return acc;
 }
 
-// Global-memory density (tiles too dense to stage): the neighbours are
-// visited in ascending index by repeatedly taking the smallest index above
-// the previous one.
+// Global-memory density (tiles too dense to stage): the window's tile lists,
+// each in ascending hit index in the CSR, are merged on the fly (cursors and
+// head indices in registers), so each query passes over its window once.
 template <int K>
 __device__ __forceinline__ float density_global(const Geom& g, const Arena& a, int64_t ubase, float xi, float yi) {
   const Window W = query_window(g, g.win_dc, xi, yi);
+  constexpr int NL = 9;  // the density window spans at most 3 x 3 tiles
+  int cur[NL], end[NL], head[NL];
+#pragma unroll
+  for (int k = 0; k < NL; ++k) {
+    const int ty = W.y0 + k / 3, tx = W.x0 + k % 3;
+    cur[k] = end[k] = 0;
+    if (ty <= W.y1 && tx <= W.x1) {
+      const int64_t t = ubase + (int64_t)ty * g.nx + tx;
+      cur[k] = a.tile_start[t];
+      end[k] = a.tile_start[t + 1];
+    }
+    head[k] = cur[k] < end[k] ? a.hs[cur[k]] : INT_MAX;
+  }
   float acc = 0.0f;
-  int last = -1;
   for (;;) {
-    int best = INT_MAX;
-    float be = 0.0f, bd = 0.0f;
-    for (int ty = W.y0; ty <= W.y1; ++ty) {
-      const int64_t t = ubase + (int64_t)ty * g.nx;
-      const int s0 = a.tile_start[t + W.x0], s1 = a.tile_start[t + W.x1 + 1];
-      for (int s = s0; s < s1; ++s) {
-        const int hj = a.hs[s];
-        const float d2 = dist2(xi, yi, a.xs[s], a.ys[s]);
-        if (hj > last && hj < best && d2 < g.dc2) {
-          best = hj;
-          be = a.es[s];
-          bd = d2;
-        }
+    int m = head[0];
+#pragma unroll
+    for (int k = 1; k < NL; ++k) m = min(m, head[k]);
+    if (m == INT_MAX) break;
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < NL; ++k)
+      if (head[k] == m) s = cur[k];
+    const float d2 = dist2(xi, yi, a.xs[s], a.ys[s]);
+    if (d2 < g.dc2) acc = __fadd_rn(acc, kernel_term<K>(d2, g.ka, a.es[s]));
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+      if (head[k] == m) {
+        ++cur[k];
+        head[k] = cur[k] < end[k] ? a.hs[cur[k]] : INT_MAX;
       }
     }
-    if (best == INT_MAX) break;
-    acc = __fadd_rn(acc, kernel_term<K>(bd, g.ka, be));
-    last = best;
   }
   return acc;
 }
@@ -1335,7 +1375,7 @@ __device__ __forceinline__ void decide_and_store(const Geom& g, const Arena& a, 
   const bool follower = !seed && !outlier && has;
   a.parent[slot] = follower ? b.p : slot;
   a.flags[slot] = (uint8_t)((seed ? F_SEED : 0) | (outlier ? F_OUTLIER : 0) | (follower ? F_FOLLOWER : 0));
-  d.is_seed[hi] = seed ? 1 : 0;
+  if (seed) atomicOr(&a.seedbits[hi >> 5], 1u << (hi & 31));
   if (follower && builds_lists(g)) a.frank[slot] = atomicAdd(&a.fstart[b.h()], 1);
   if (g.flags & 2u) {
     a.nh_out[hi] = has ? b.h() - ev_first : -1;
@@ -1658,7 +1698,7 @@ __global__ __launch_bounds__(kWG) void k_label(DescArg<G> dg, Geom g, Arena a) {
       int lab = -1;
       if ((in ? s_fl[r[j] - c0] : a.flags[r[j]]) & F_SEED) {
         const int e = d.event ? clampi(d.event[hsj[j]] - d.event_base, 0, d.n_events - 1) : 0;
-        lab = a.seed_rank[in ? s_hs[r[j] - c0] : a.hs[r[j]]] - a.seed_rank[event_first_hit(a, d, e)];
+        lab = seed_rank(a, in ? s_hs[r[j] - c0] : a.hs[r[j]]) - seed_rank(a, event_first_hit(a, d, e));
       }
       d.cluster_id[hsj[j]] = lab;
     }
@@ -1712,8 +1752,8 @@ __global__ __launch_bounds__(kWG) void k_expand_init(DescArg<G> dg, Geom g, Aren
         a.rank[h[j]] = r;
       } else if (f[j] & F_SEED) {
         const int e = d.event ? clampi(d.event[h[j]] - d.event_base, 0, d.n_events - 1) : 0;
-        const int rk = a.seed_rank[h[j]];
-        lab = rk - a.seed_rank[event_first_hit(a, d, e)];
+        const int rk = seed_rank(a, h[j]);
+        lab = rk - seed_rank(a, event_first_hit(a, d, e));
         seeds[rk] = h[j];
       }
       d.cluster_id[h[j]] = lab;
@@ -1730,7 +1770,7 @@ template <bool G>
 __global__ __launch_bounds__(kWG) void k_expand_dfs(DescArg<G> dg, Geom g, Arena a) {
   const RunDesc d = dg.get();
   const int* const seeds = reinterpret_cast<const int*>(a.xs);
-  const int ns = a.seed_rank[d.n];
+  const int ns = seed_rank(a, d.n);
   const int64_t max_steps = 2 * ((int64_t)d.n + 1);
   for (int t = blockIdx.x * kWG + (int)threadIdx.x; t < ns; t += gridDim.x * kWG) {
     const int root = seeds[t];
@@ -1769,8 +1809,9 @@ __global__ __launch_bounds__(kWG) void k_expand_dfs(DescArg<G> dg, Geom g, Arena
 }
 
 // Follower lists: sort each list by hit index, then make indices event-local.
-// Lists of up to kShortList entries are sorted in registers (an odd-even
-// transposition network); longer ones by insertion in place.
+// Lists of up to kShortList entries are sorted in registers (odd-even
+// transposition networks of four entries, when every list of the wave fits,
+// or eight); longer ones by insertion in place.
 constexpr int kShortList = 8;
 
 template <bool G>
@@ -1793,10 +1834,30 @@ __global__ __launch_bounds__(kWG) void k_follow_sort(DescArg<G> dg, Geom g, Aren
 #pragma unroll
     for (int j = 0; j < U; ++j) {
       const int len = end[j] - b[j];
+      // nearly every wave holds only lists of up to four entries: then the
+      // whole wave takes the shorter network (a wave-uniform choice)
+      const bool four = __all(len <= 4);
       if (len == 0) continue;
       const int h = hb + j * kWG;
       const int e = d.event ? clampi(d.event[h] - d.event_base, 0, d.n_events - 1) : 0;
       const int off = event_first_hit(a, d, e);
+      if (four) {
+        int v[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[i] = i < len ? a.flist[b[j] + i] : INT_MAX;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int i = r & 1; i + 1 < 4; i += 2) {
+            const int lo = min(v[i], v[i + 1]), hi = max(v[i], v[i + 1]);
+            v[i] = lo;
+            v[i + 1] = hi;
+          }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (i < len) a.flist[b[j] + i] = v[i] - off;
+        continue;
+      }
       if (len <= kShortList) {
         int v[kShortList];
 #pragma unroll

@@ -306,3 +306,41 @@ def test_decreasing_event_ids_without_validation():
         good = gen.concat_events([a, b])
         got = gpu_run(good, p, batched=True, n_events=2, ctx=ctx)
     assert_parity(got, _ref(good, p), where="valid batch after decreasing ids")
+
+
+def test_dense_core_takes_the_global_merge_and_scales():
+    """A core far denser than any LDS cap: m hits inside one tile, all within
+    dc of one another, so every query has about m neighbours and exact
+    densities need O(m^2) work in all. The global-memory path merges the
+    window's index-sorted tile lists once per query; the run stays bit-exact
+    and doubling m costs well under the 8x a rescan of the window per
+    neighbour would."""
+    import torch
+    import paper_2001_09761_amd as clue
+    from gpu_helpers import to_dev
+    times = {}
+    for m in (4000, 8000):
+        rng = np.random.default_rng(m)
+        x = rng.normal(10.0, 0.3, m).astype(np.float32)
+        y = rng.normal(10.0, 0.3, m).astype(np.float32)
+        ev = dict(x=x, y=y, layer=np.zeros(m, np.int32), energy=rng.uniform(0.5, 1.5, m).astype(np.float32))
+        p = dict(ADV_P, n_layers=1)
+        print(f"dense core: m = {m}", flush=True)
+        assert_parity(gpu_run(ev, p), _ref(ev, p), where=f"dense core m={m}")
+        t = to_dev(ev, torch.device("cuda", 0))
+        with clue.Context(p["dc"], p["rho_c"], p["delta_c"], p["delta_o"], max_hits=m, bounds=p["bounds"],
+                          n_layers=1) as ctx:
+            ctx.run(t["x"], t["y"], t["layer"], t["energy"])
+            ms = []
+            for _ in range(5):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                ctx.run(t["x"], t["y"], t["layer"], t["energy"])
+                e1.record()
+                e1.synchronize()
+                ms.append(e0.elapsed_time(e1))
+            ctx.status()
+        times[m] = float(np.median(ms))
+    print(f"dense core device ms: {times}", flush=True)
+    assert times[8000] < 6.0 * times[4000], times
