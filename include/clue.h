@@ -99,13 +99,20 @@ typedef struct clue_ctx clue_ctx;
  * Create a context on HIP device `hip_device` with scratch for up to
  * `max_hits` hits in up to `max_events` events per run. hbm_budget_bytes > 0
  * caps the arena size (CLUE_ERR_BUDGET if the capacity does not fit); 0 means
- * no cap. Allocates device memory synchronously. *out is NULL on failure.
+ * no cap. Allocates device memory synchronously, once, outside the runs: the
+ * paper allocates its device buffers once for all events and leaves that
+ * allocation out of its timings (Sec. 4.2). *out is NULL on failure.
  */
 int clue_create(clue_ctx **out, const clue_params *p, int hip_device, int64_t max_hits,
                 int32_t max_events, uint64_t hbm_budget_bytes);
 
-/* Grow the arena to at least (max_hits, max_events). Synchronous: call it
- * outside timed regions. Invalidates captured graphs (re-captured lazily). */
+/* Grow the arena to at least (max_hits, max_events): the one-time
+ * allocation of Sec. 4.2 redone for a larger capacity. Synchronous: call it
+ * outside timed regions. Invalidates captured graphs (re-captured lazily).
+ * CLUE_ERR_ARG for a capacity out of range; CLUE_ERR_BUDGET if the larger
+ * arena exceeds the HBM budget (the old arena is kept); CLUE_ERR_NOMEM if its
+ * allocation fails (the old arena is already freed: runs are then refused
+ * with CLUE_ERR_CAPACITY until a clue_reserve succeeds). */
 int clue_reserve(clue_ctx *c, int64_t max_hits, int32_t max_events);
 
 /* Bytes of device memory a context with this capacity allocates (arena plus
@@ -127,9 +134,13 @@ int clue_run(clue_ctx *c, int64_t n, const float *x, const float *y, const int32
  * Cluster a batch of n hits from n_events events in one pass ("batched"
  * form): event int32[n] holds each hit's event id, non-decreasing, in
  * [0, n_events); the other arrays are as in clue_run. Indices and cluster ids
- * are event-local, identical to running each event alone. Runs one persistent
- * kernel per stage over a device work queue of (event, layer, tile block)
- * items, replayed from a captured HIP graph.
+ * are event-local, identical to running each event alone. Sec. 3 processes
+ * all layers of one event in each kernel launch; this extends that to many
+ * events: one persistent kernel per stage over a device work queue of
+ * (event, layer, tile block) items, replayed from a captured HIP graph.
+ * Errors as clue_run, plus CLUE_ERR_ARG for a null `event` with n_events > 1;
+ * ids out of range or decreasing are caught only with CLUE_VALIDATE (without
+ * it the run stays within its buffers, with unspecified results).
  */
 int clue_run_batch(clue_ctx *c, int64_t n, int32_t n_events, const int32_t *event, const float *x,
                    const float *y, const int32_t *layer, const float *energy, int32_t *cluster_id,

@@ -199,7 +199,7 @@ struct ArenaPlan {
 };
 
 enum {
-  A_KEY, A_RANK, A_TS, A_XS, A_YS, A_ES, A_HS, A_RHO, A_PARENT, A_FLAGS, A_SEEDRANK, A_EVSTART, A_FSTART,
+  A_KEY, A_RANK, A_TS, A_XS, A_YS, A_ES, A_HS, A_RHO, A_PARENT, A_FLAGS, A_SEEDBITS, A_SEEDW, A_EVSTART, A_FSTART,
   A_FRANK, A_FLIST, A_RHO_OUT, A_NH_OUT, A_D2_OUT, A_STATUS, A_COUNTERS, A_ERR, A_DESC, A_NUM
 };
 
@@ -218,7 +218,7 @@ static bool plan_arena(const Geom& g, int64_t N, int32_t E, ArenaPlan& P) {
   sz[A_RHO] = 4 * n;
   sz[A_PARENT] = 4 * n;
   sz[A_FLAGS] = n;
-  sz[A_SEEDRANK] = 4 * (n + 1) + 64;
+  sz[A_SEEDBITS] = sz[A_SEEDW] = 4 * (n / 32 + 2) + 64;
   sz[A_EVSTART] = 4 * ((size_t)E + 1);
   sz[A_FSTART] = fol ? 4 * (n + 1) + 64 : 0;
   sz[A_FRANK] = fol ? 4 * n : 0;
@@ -254,7 +254,8 @@ static Arena arena_at(char* b, const Geom& g, const ArenaPlan& P, int64_t N, int
   a.rho = (float*)(b + P.off[A_RHO]);
   a.parent = (int32_t*)(b + P.off[A_PARENT]);
   a.flags = (uint8_t*)(b + P.off[A_FLAGS]);
-  a.seed_rank = (int32_t*)(b + P.off[A_SEEDRANK]);
+  a.seedbits = (uint32_t*)(b + P.off[A_SEEDBITS]);
+  a.seed_wrank = (int32_t*)(b + P.off[A_SEEDW]);
   a.ev_start = (int32_t*)(b + P.off[A_EVSTART]);
   a.fstart = fol ? (int32_t*)(b + P.off[A_FSTART]) : nullptr;
   a.frank = fol ? (int32_t*)(b + P.off[A_FRANK]) : nullptr;
@@ -311,6 +312,11 @@ static int alloc_arena(clue_ctx* c, int64_t N, int32_t E) {
     drop_graph(c);
     void* old = c->arena_base;
     c->arena_base = nullptr;
+    // until the new arena is bound the context holds nothing: a run that
+    // follows a failed allocation is refused for capacity
+    c->a = Arena{};
+    c->arena_bytes = 0;
+    c->last_n = -1;
     HIP_TRY(c, hipFree(old));
   }
   hipError_t e = hipMalloc(&c->arena_base, P.total);
@@ -709,6 +715,7 @@ int clue_status(clue_ctx* c, void* stream) {
   if (!c) return CLUE_ERR_ARG;
   HIP_TRY(c, hipSetDevice(c->device));
   HIP_TRY(c, hipStreamSynchronize((hipStream_t)stream));
+  if (!c->a.err) return CLUE_OK;  // no arena bound (a failed reallocation)
   uint32_t err = 0;
   HIP_TRY(c, hipMemcpy(&err, c->a.err, sizeof err, hipMemcpyDeviceToHost));
   if (err) {
