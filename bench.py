@@ -245,9 +245,18 @@ def main():
                     help="reduce rocprofv3 --pmc runs under DIR (fetch/, write/, copy_fetch/, copy_write/) "
                          "to the per-launch HBM traffic of the dominant kernel and write it to profiles/")
     ap.add_argument("--stage", default="density", help="stage whose kernel --traffic-summary reduces")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="run only a served stream (config 5) at --serve-rate for --serve-events arrivals, or with "
+                         "--serve-rate 0 a 64-event burst through the online Server (short enough to trace)")
+    ap.add_argument("--overlap-summary", metavar="DIR",
+                    help="reduce a rocprofv3 --kernel-trace run under DIR to the fraction of time in which "
+                         "kernels of two or more streams are in flight")
     args = ap.parse_args()
     if args.traffic_summary:
         traffic_summary(args.traffic_summary, args.stage, args.events)
+        return
+    if args.overlap_summary:
+        print(json.dumps(overlap_summary(args.overlap_summary)))
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); independent events would shard "
@@ -263,6 +272,9 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     log = lambda s: print(s, file=sys.stderr, flush=True)  # noqa: E731
+    if args.serve_only:
+        print(json.dumps(serve_only(args, log)), flush=True)
+        return
 
     if args.calibrate_copy:
         # one elementwise kernel reading 1 GiB and writing 1 GiB, five times
@@ -692,6 +704,97 @@ def host_resident(events, params, log):
     log(f"host-resident: one chunk {out['one_chunk']['ms_per_batch']} ms, chunked "
         f"{out['chunks_of_8_events']['ms_per_batch']} ms")
     return out
+
+
+def serve_only(args, log):
+    """A served Poisson stream over a device pool of the 64 config-4 events
+    (replicated to cover the arrivals) at one offered rate, or (rate 0) the
+    same events as one burst through the online Server: two slots on two
+    streams either way. Used under a kernel trace to see the slots overlap."""
+    import numpy as np
+    import torch
+
+    import paper_2001_09761_amd as clue
+    from paper_2001_09761_amd import gen
+    from paper_2001_09761_amd.serve import GpuPoolBackend, Scheduler
+
+    dev = torch.device("cuda", 0)
+    params = dict(gen.DEFAULT_PARAMS, extent=200.0, n_layers=100)
+    evs = [gen.config4_event(e) for e in range(64)]
+    b = gen.concat_events(evs)
+    n_arr = int(args.serve_events)
+    pool = replicated_pool(b, (n_arr + 63) // 64, dev)
+    n_hits = np.diff(pool["offsets"]).tolist()
+    cap = 8 * max(n_hits)
+    d = {k: torch.from_numpy(b[k][:cap]).to(dev) for k in ("event", "x", "y", "layer", "energy")}
+    with clue.Context(params["dc"], params["rho_c"], params["delta_c"], params["delta_o"], max_hits=cap,
+                      max_events=8, extent=200.0, n_layers=100) as ctx:
+        tuning, _ = apply_tuning(ctx, d, 8, params, log)
+    del d
+    out = {}
+    if args.serve_rate > 0:
+        be = GpuPoolBackend(params, pool, slots=2, max_batch_hits=cap, max_batch_events=8,
+                            tuning=tuning_kwargs(tuning))
+        st = Scheduler(be, hbm_budget_bytes=0, max_batch_hits=cap, max_batch_events=8).run(
+            gen.poisson_arrivals(args.serve_rate, n_arr), n_hits[:n_arr])
+        torch.cuda.synchronize()
+        be.close()
+        out["serving"] = {"offered_events_per_s": args.serve_rate, "arrivals": n_arr,
+                          **{k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.summary().items()}}
+        log(f"serve-only: {out}")
+        return out
+    offs = pool["offsets"]
+    views = [tuple(pool[k][int(offs[i]):int(offs[i + 1])] for k in ("x", "y", "layer", "energy")) for i in range(64)]
+    with clue.Server(params["dc"], params["rho_c"], params["delta_c"], params["delta_o"], max_batch_hits=cap,
+                     max_batch_events=8, slots=2, extent=200.0, n_layers=100, tuning=tuning_kwargs(tuning)) as srv:
+        t0 = time.perf_counter()
+        for f in [srv.submit(*v) for v in views]:
+            f.result()
+        out["online_burst"] = {"events": 64, "wall_ms": round((time.perf_counter() - t0) * 1e3, 3)}
+    log(f"serve-only: {out}")
+    return out
+
+
+def overlap_summary(d):
+    """From a rocprofv3 kernel trace (CSV) under d: per stream (or queue), the
+    union of its kernels' execution intervals; the share of the traced span
+    in which two or more streams have a kernel in flight, and of the time in
+    which any kernel runs."""
+    import csv
+    import glob
+    files = glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no kernel_trace.csv under {d}")
+    rows = []
+    for f in files:
+        with open(f) as fh:
+            rows += list(csv.DictReader(fh))
+    key = "Stream_Id" if rows and "Stream_Id" in rows[0] else "Queue_Id"
+    events = []
+    streams = {}
+    for r in rows:
+        if "clue::" not in r["Kernel_Name"]:
+            continue
+        s, t0, t1 = r[key], int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+        streams[s] = streams.get(s, 0) + 1
+        events += [(t0, 1, s), (t1, -1, s)]
+    events.sort()
+    active = {}
+    busy = both = 0
+    last = events[0][0] if events else 0
+    for t, dv, s in events:
+        k = sum(1 for v in active.values() if v > 0)
+        if k >= 1:
+            busy += t - last
+        if k >= 2:
+            both += t - last
+        active[s] = active.get(s, 0) + dv
+        last = t
+    span = (events[-1][0] - events[0][0]) if events else 0
+    return {"grouped_by": key, "kernels_per_stream": streams, "span_ms": span / 1e6,
+            "busy_ms": busy / 1e6, "two_or_more_in_flight_ms": both / 1e6,
+            "frac_of_span_two_or_more": both / span if span else 0.0,
+            "frac_of_busy_two_or_more": both / busy if busy else 0.0}
 
 
 def replicated_pool(batch, reps, dev):
