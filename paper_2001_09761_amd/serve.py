@@ -507,9 +507,16 @@ def plan_batch(sizes, max_hits, max_events):
 
 
 class _Slot:
-    def __init__(self, ctx, stream):
+    """One context, its stream, and its batch input columns (allocated once,
+    max_batch_hits long): events are copied into them at their offsets."""
+
+    def __init__(self, ctx, stream, max_hits, device):
+        import torch
         self.ctx = ctx
         self.stream = stream
+        self.inputs = {k: torch.empty(max_hits, dtype=dt, device=device) for k, dt in
+                       (("x", torch.float32), ("y", torch.float32), ("layer", torch.int32),
+                        ("energy", torch.float32), ("event", torch.int32))}
 
 
 class Server:
@@ -518,13 +525,15 @@ class Server:
     (int32 and uint8 device tensors, event-local as from ``Context.run``).
 
     A worker thread takes queued events in arrival order and, whenever one of
-    the ``slots`` is free, gathers a batch of them (up to ``max_batch_hits``
-    hits and ``max_batch_events`` events) into one tensor per input and runs
-    the batched form on the slot's own stream; slots overlap on the GPU. Each
+    the ``slots`` is free, copies a batch of them (up to ``max_batch_hits``
+    hits and ``max_batch_events`` events) into the slot's input columns and
+    runs the batched form on the slot's own stream; slots overlap on the GPU. Each
     event's result is a view of its batch's output tensors. The device memory
     the server works in is bounded when it is built (per slot: the context
-    arena plus one batch of inputs and outputs) and must fit ``hbm_budget``
-    bytes (0: no limit); events wait in the queue until a slot takes them.
+    arena, the slot's batch input columns, allocated once, into which events
+    are copied at their offsets, and one batch of outputs) and must fit
+    ``hbm_budget`` bytes (0: no limit); events wait in the queue until a slot
+    takes them.
 
     Inputs may be torch tensors on the server's device or on the host, or
     numpy arrays. Device inputs are read on the slot's stream after the work
@@ -565,15 +574,15 @@ class Server:
                               flags=flags, device=self.device.index, kernel=kernel, kernel_scale=kernel_scale)
                 if tuning:
                     ctx.set_tuning(**tuning)
-                sl = _Slot(ctx, torch.cuda.Stream(device=self.device))  # default priority
+                sl = _Slot(ctx, torch.cuda.Stream(device=self.device), self.max_batch_hits, self.device)
                 self._slots.append(sl)
-                # one full batch of inputs and outputs, allocated and released on
-                # the slot's stream, leaves its blocks in torch's cache for the
-                # batches to come (the first batches then allocate nothing new)
+                # one full batch of outputs, allocated and released on the slot's
+                # stream, leaves its blocks in torch's cache for the batches to
+                # come (the first batches then allocate nothing new)
                 with torch.cuda.stream(sl.stream):
                     m = self.max_batch_hits
-                    warm = [torch.empty(m, dtype=dt, device=self.device)
-                            for dt in (torch.float32,) * 3 + (torch.int32,) * 3 + (torch.uint8,)]
+                    warm = [torch.empty(m, dtype=torch.int32, device=self.device),
+                            torch.empty(m, dtype=torch.uint8, device=self.device)]
                     del warm
         except Exception:
             for sl in self._slots:
@@ -624,17 +633,19 @@ class Server:
             for _, _, ready, _ in items:
                 if ready is not None:
                     sl.stream.wait_event(ready)
-            # one batch tensor per input column (a few launches per batch, not per event)
-            cols = list(zip(*[[t.to(dev, non_blocking=True) for t in it[1]] for it in items]))
-            x, y, layer, energy = (torch.cat(c) if k > 1 else c[0] for c in cols)
-            sizes = [it[0] for it in items]
-            total = int(sum(sizes))
-            counts = torch.tensor(sizes, dtype=torch.int64).pin_memory().to(dev, non_blocking=True)
-            event = torch.repeat_interleave(torch.arange(k, dtype=torch.int32, device=dev), counts,
-                                            output_size=total)
+            # each event's columns go straight into the slot's batch columns
+            cols = sl.inputs
+            a = 0
+            for i, (n, ins, _, _) in enumerate(items):
+                for name, t in zip(("x", "y", "layer", "energy"), ins):
+                    cols[name][a:a + n].copy_(t, non_blocking=True)
+                cols["event"][a:a + n].fill_(i)
+                a += n
+            total = a
             cid = torch.empty(total, dtype=torch.int32, device=dev)
             seed = torch.empty(total, dtype=torch.uint8, device=dev)
-            sl.ctx.run_batch(event, k, x, y, layer, energy, cid, seed, stream=sl.stream)
+            sl.ctx.run_batch(cols["event"][:total], k, cols["x"][:total], cols["y"][:total], cols["layer"][:total],
+                             cols["energy"][:total], cid, seed, stream=sl.stream)
             done = torch.cuda.Event()
             done.record(sl.stream)
         # each event's result is a view of the batch outputs
@@ -642,7 +653,7 @@ class Server:
         for n, _, _, fut in items:
             outs.append((fut, cid[a:a + n], seed[a:a + n]))
             a += n
-        return done, outs, (items, x, y, layer, energy, event)
+        return done, outs, items
 
     def _finish(self, slot, outs, err=None):
         if err is None and self._validate:
