@@ -958,6 +958,7 @@ __device__ __forceinline__ float4 rec_at(const float4* rec, int byte_off) {
   return *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(rec) + byte_off);
 }
 static_assert(kMaxLdsCap * 16 <= 65536, "quad-list byte offsets are 16-bit");
+static_assert(kMaxRegionRows <= 64 && kMaxRegionTiles <= 1024, "a staged tile id is (row << 10) | column in 16 bits");
 
 // Density over a staged region (records x, y, E, index; each tile in
 // ascending hit index). With MAXL == 2 every query window lies inside the
@@ -972,12 +973,15 @@ __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, co
   const int per_row = R.rw + 1;
   const int64_t ubase = (int64_t)R.unit * g.tpl;
   const int ntl = R.rh * per_row;
-  // region tile of every staged position, two lanes per tile
+  // region tile of every staged position as (row << 10) | column (rows
+  // < 64, columns < 1024), two lanes per tile
   for (int k = threadIdx.x; k < 2 * ntl; k += kWG) {
     const int tl = k >> 1;
-    if (tl % per_row == R.rw) continue;  // row-end entry
+    const int tr = tl / per_row, tc = tl - tr * per_row;
+    if (tc == R.rw) continue;  // row-end entry
+    const unsigned short code = (unsigned short)((tr << 10) | tc);
     const int end = L.ts[tl + 1];
-    for (int p = L.ts[tl] + (k & 1); p < end; p += 2) stile[p] = (unsigned short)tl;
+    for (int p = L.ts[tl] + (k & 1); p < end; p += 2) stile[p] = code;
   }
   __syncthreads();
   // copy the records (tiles are already in ascending hit index); every
@@ -988,7 +992,7 @@ __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, co
     for (int k = 0; k < kStagePer; ++k) {
       const int p = base + (int)threadIdx.x + k * kWG;
       if (p < R.total) {
-        const int sl = slot_of(L, stile[p] / per_row, p);
+        const int sl = slot_of(L, stile[p] >> 10, p);
         v[k] = make_float4(a.xs[sl], a.ys[sl], a.es[sl], __int_as_float(a.hs[sl]));
       }
     }
@@ -1070,8 +1074,8 @@ __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, co
     // of the quad, the entries with a smaller hit index (each of the up to
     // eight neighbour tiles is counted once and shared by the quads)
     for (int p = threadIdx.x; p < R.total; p += kWG) {
-      const int tl = stile[p];
-      const int tr = tl / per_row, tc = tl - tr * per_row;
+      const int tr = stile[p] >> 10, tc = stile[p] & 1023;
+      const int tl = tr * per_row + tc;
       const int hp = rec_key(rec, p);
       const int own = p - L.ts[tl];
       bool qv[2][2];
