@@ -44,6 +44,13 @@ ALG_BYTES = {
 }
 PIPELINE_ALG_BYTES = 85.0
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "density_1M-hit-x32_traffic.json")
+PROFILE_ISSUE = os.path.join(ROOT, "profiles", "density_1M-hit-x32_valu_issue.json")
+# Non-packed FP32 issue ceiling: the published 157.3 TFLOP/s FP32 vector peak is
+# 256 CUs x 2.4 GHz x 256 flop per CU-cycle with packed two-wide FMAs, i.e. one
+# wave64 instruction per CU-cycle without packing (the kernels are built without it).
+CU_COUNT = 256
+CLOCK_GHZ = 2.4
+VALU_ISSUE_CEILING = 1.0  # wave64 VALU instructions per CU-cycle
 
 
 def kernel_source_sha() -> str:
@@ -244,6 +251,9 @@ def main():
     ap.add_argument("--traffic-summary", metavar="DIR",
                     help="reduce rocprofv3 --pmc runs under DIR (fetch/, write/, copy_fetch/, copy_write/) "
                          "to the per-launch HBM traffic of the dominant kernel and write it to profiles/")
+    ap.add_argument("--issue-summary", metavar="DIR",
+                    help="reduce a rocprofv3 --pmc SQ_INSTS_VALU run under DIR/sq with the kernel trace under "
+                         "DIR/ktrace to the VALU issue rate of the dominant kernel and write it to profiles/")
     ap.add_argument("--stage", default="density", help="stage whose kernel --traffic-summary reduces")
     ap.add_argument("--serve-only", action="store_true",
                     help="run only a served stream (config 5) at --serve-rate for --serve-events arrivals, or with "
@@ -254,6 +264,9 @@ def main():
     args = ap.parse_args()
     if args.traffic_summary:
         traffic_summary(args.traffic_summary, args.stage, args.events)
+        return
+    if args.issue_summary:
+        issue_summary(args.issue_summary, args.stage, args.events)
         return
     if args.overlap_summary:
         print(json.dumps(overlap_summary(args.overlap_summary)))
@@ -408,9 +421,25 @@ def main():
                                     "source": os.path.relpath(PROFILE_TRAFFIC, ROOT)}
     except (OSError, ValueError, KeyError):
         traffic = None
+    # how close the kernel runs to its issue ceiling: SQ_INSTS_VALU per launch
+    # from the committed profile of the same kernel source, over this run's
+    # launch duration
+    valu_issue = None
+    try:
+        iss = json.load(open(PROFILE_ISSUE))
+        if iss.get("kernel_source_sha") == kernel_source_sha() and iss.get("stage") == dom \
+                and int(iss.get("hits_per_launch", -1)) == n:
+            per_cycle = iss["sq_insts_valu_per_launch"] / (CU_COUNT * dom_ms * 1e-3 * CLOCK_GHZ * 1e9)
+            valu_issue = {"valu_insts_per_cu_cycle": round(per_cycle, 3), "ceiling": VALU_ISSUE_CEILING,
+                          "frac": round(per_cycle / VALU_ISSUE_CEILING, 3),
+                          "lane_slots_per_hit": round(iss["sq_insts_valu_per_launch"] * 64 / n, 1),
+                          "source": os.path.relpath(PROFILE_ISSUE, ROOT)}
+    except (OSError, ValueError, KeyError):
+        valu_issue = None
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
-                "alg_bytes_per_hit": ALG_BYTES[dom], "hits_per_launch": n, "avg_launch_ms": round(dom_ms, 4)}
+                "alg_bytes_per_hit": ALG_BYTES[dom], "hits_per_launch": n, "avg_launch_ms": round(dom_ms, 4),
+                "valu_issue": valu_issue}
     # the Gaussian and exponential kernels of Eq. 3 on the same batch and tuning
     kernels = {}
     if not args.no_extras:
@@ -553,6 +582,41 @@ def traffic_summary(d, stage, n_events, out_path=None):
            "hbm_bytes_per_hit": hbm / hits, "alg_bytes_per_hit": ALG_BYTES[stage],
            "per_stage_hbm_bytes_per_launch": per_stage}
     with open(out_path or PROFILE_TRAFFIC, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out))
+
+
+def issue_summary(d, stage, n_events, out_path=None):
+    """VALU issue of one stage's batched kernel: SQ_INSTS_VALU per dispatch
+    (mean over its dispatches, from a --pmc run under d/sq) and its average
+    duration from a --kernel-trace --stats run under d/ktrace, against one
+    wave64 instruction per CU-cycle."""
+    import csv
+    import glob
+    kname = STAGE_KERNEL[stage]
+    valu, nv = _mean_counter(_pmc_rows(os.path.join(d, "sq")), "SQ_INSTS_VALU", kname)
+    durs = []
+    for f in glob.glob(os.path.join(d, "ktrace", "**", "*kernel_stats.csv"), recursive=True):
+        with open(f) as fh:
+            durs += [float(r["AverageNs"]) for r in csv.DictReader(fh) if kname in r["Name"]]
+    if not durs:
+        raise SystemExit(f"no kernel stats for {kname!r} under {d}/ktrace")
+    ns = durs[0]
+    per_cycle = valu / (CU_COUNT * ns * 1e-9 * CLOCK_GHZ * 1e9)
+    hits = 10000 * 100 * n_events
+    out = {"stage": stage, "kernel_match": kname, "kernel_source_sha": kernel_source_sha(),
+           "hits_per_launch": hits, "sq_insts_valu_per_launch": valu, "dispatches": nv,
+           "avg_duration_ns": ns, "valu_insts_per_cu_cycle": per_cycle, "ceiling": VALU_ISSUE_CEILING,
+           "commands": {
+               "sq": "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc SQ_INSTS_VALU SQ_INSTS_LDS "
+                     "SQ_LDS_BANK_CONFLICT SQ_ACTIVE_INST_LDS SQ_WAIT_INST_LDS SQ_BUSY_CYCLES SQ_WAVE_CYCLES "
+                     "SQ_ACTIVE_INST_VALU --output-format csv -d <out>/sq -o run -- python3 <repo>/bench.py "
+                     "--steps 2 --warmup 1 --no-cpu --no-extras",
+               "ktrace": "cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats --output-format csv "
+                         "-d <out>/ktrace -o run -- python3 <repo>/bench.py --steps 10 --warmup 3 --no-cpu "
+                         "--no-extras",
+               "reduce": "python3 <repo>/bench.py --issue-summary <out>"}}
+    with open(out_path or PROFILE_ISSUE, "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps(out))
 

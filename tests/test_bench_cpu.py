@@ -1,6 +1,6 @@
 """bench.py's host logic on the CPU: the one-GPU guard, the reduction of
-rocprofv3 counter files to per-launch HBM traffic (copy-calibrated), and the
-tuning-to-arguments conversion."""
+rocprofv3 counter files to per-launch HBM traffic (copy-calibrated) and to the
+VALU issue rate, and the tuning-to-arguments conversion."""
 import csv
 import json
 import os
@@ -52,6 +52,24 @@ def test_traffic_summary_scales_by_the_copy_calibration(tmp_path):
     assert t["per_stage_hbm_bytes_per_launch"]["labels"] == pytest.approx(50.0 * 1024 * 2 + 25.0 * 1024)
     assert "grid_hist" not in t["per_stage_hbm_bytes_per_launch"]
     assert t["kernel_source_sha"] == bench.kernel_source_sha()
+
+
+def test_issue_summary_divides_valu_by_cu_cycles(tmp_path):
+    dens = "void clue::k_density<true, 2, 0>(clue::DescArg<true>, clue::Geom, clue::Arena)"
+    _write(tmp_path / "sq", "SQ_INSTS_VALU", [(dens, 6.0e8), (dens, 6.2e8),
+                                             ("void clue::k_density<false, 2, 0>(x)", 1.0)])
+    os.makedirs(tmp_path / "ktrace")
+    with open(tmp_path / "ktrace" / "run_kernel_stats.csv", "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Name", "Calls", "AverageNs"])
+        w.writeheader()
+        w.writerow({"Name": dens, "Calls": 10, "AverageNs": 1.0e6})
+    out = tmp_path / "issue.json"
+    bench.issue_summary(str(tmp_path), "density", 32, out_path=str(out))
+    t = json.loads(out.read_text())
+    assert t["sq_insts_valu_per_launch"] == pytest.approx(6.1e8)
+    # 256 CUs x 1 ms x 2.4 GHz = 6.144e8 CU-cycles
+    assert t["valu_insts_per_cu_cycle"] == pytest.approx(6.1e8 / 6.144e8)
+    assert t["kernel_source_sha"] == bench.kernel_source_sha() and t["hits_per_launch"] == 32 * 10 ** 6
 
 
 def test_tuning_kwargs():
