@@ -72,6 +72,31 @@ def test_issue_summary_divides_valu_by_cu_cycles(tmp_path):
     assert t["kernel_source_sha"] == bench.kernel_source_sha() and t["hits_per_launch"] == 32 * 10 ** 6
 
 
+def test_overlap_summary_measures_time_with_two_streams_busy(tmp_path):
+    # stream 1 runs [0, 10) and [20, 30), stream 2 runs [5, 25): both are busy
+    # in [5, 10) and [20, 25), some stream in [0, 30); non-CLUE kernels are ignored
+    rows = [("clue::k_density", 1, 0, 10), ("clue::k_label", 1, 20, 30), ("clue::k_hist", 2, 5, 25),
+            ("at::native::neg_kernel", 3, 0, 30)]
+    with open(tmp_path / "run_kernel_trace.csv", "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Kernel_Name", "Stream_Id", "Start_Timestamp", "End_Timestamp"])
+        w.writeheader()
+        for name, st, t0, t1 in rows:
+            w.writerow({"Kernel_Name": name, "Stream_Id": st, "Start_Timestamp": t0 * 10 ** 6,
+                        "End_Timestamp": t1 * 10 ** 6})
+    o = bench.overlap_summary(str(tmp_path))
+    assert o["kernels_per_stream"] == {"1": 2, "2": 1}
+    assert o["span_ms"] == pytest.approx(30.0) and o["busy_ms"] == pytest.approx(30.0)
+    assert o["two_or_more_in_flight_ms"] == pytest.approx(10.0)
+    assert o["frac_of_busy_two_or_more"] == pytest.approx(1 / 3)
+
+
+def test_linear_fit_recovers_a_line():
+    xs = [1e5 * k for k in range(1, 11)]
+    f = bench.linear_fit(xs, [0.2 + 0.13e-6 * x for x in xs])
+    assert f["slope_ms_per_Mhit"] == pytest.approx(0.13) and f["intercept_ms"] == pytest.approx(0.2)
+    assert f["r2"] == pytest.approx(1.0)
+
+
 def test_tuning_kwargs():
     t = {"block": (10, 8), "tile_size": 4.0, "lds_cap": 768, "plain_lds_cap": 960, "ms": 4.8, "density_quads": 1}
     kw = bench.tuning_kwargs(t)
