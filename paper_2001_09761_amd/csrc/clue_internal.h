@@ -38,7 +38,9 @@ enum Counter {
   C_TICKET_SEEDS = 1 * kCounterStride,          // chunk tickets of the seed / follower scan
   C_QUEUE_RHO = 2 * kCounterStride,             // kQueues heads for the density stage
   C_QUEUE_NH = (2 + kQueues) * kCounterStride,  // kQueues heads for the nearest-higher stage
-  C_COUNT = (2 + 2 * kQueues) * kCounterStride
+  C_SPILL_RHO = (2 + 2 * kQueues) * kCounterStride,      // density query chunks left to the spill kernel
+  C_SPILL_NH = (2 + 2 * kQueues + 1) * kCounterStride,   // ... and nearest-higher query chunks
+  C_COUNT = (2 + 2 * kQueues + 2) * kCounterStride
 };
 
 // Device error word bits (read and cleared by clue_status).
@@ -103,6 +105,9 @@ __host__ __device__ inline bool builds_lists(const Geom& g) { return !(g.flags &
 struct Arena {
   int32_t* key;          // [N]   caller order: global tile id of each hit
   int32_t* rank;         // [N]   caller order: arrival rank within its tile
+                         //       (free after the grid build: the spill queues of the
+                         //       density and nearest-higher stages, tile and first slot
+                         //       of each query chunk)
                          //       (the depth-first expansion reuses both for each
                          //       follower's owner and its position in the owner's list)
                          //       (the grid build keeps arrival-order hit ids and tiles

@@ -9,8 +9,11 @@
 //   k_density          rho (Eq. 3, Algorithm 1) over LDS-staged tile windows,
 //                      summed in ascending hit index along merged 2x2-tile
 //                      lists of the index-ordered tiles
+//   k_density_spill    rho of the queries in tiles too dense for LDS, queued by
+//                      k_density and spread over the whole GPU
 //   k_nearest_higher   nh / delta (Eq. 4, Algorithm 2) fused with the seed /
 //                      outlier / follower decision (Sec. 2.2, Algorithm 3)
+//   k_nh_spill         the same for the queries that k_nearest_higher queued
 //   k_scan<SEEDS>      seed numbering by prefix scan over the seed bitmap (and
 //                      follower list offsets); writes the caller-order seed flags
 //   k_label            cluster ids: each hit follows nearest-higher links of
@@ -1213,15 +1216,39 @@ __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, co
   }
 }
 
-template <int K>
-__device__ __forceinline__ void density_global_region(const Geom& g, const Arena& a, const Region& R, const RegionLds& L, bool keep) {
+// Regions whose tiles are too dense for LDS are not searched by the workgroup
+// that meets them: their core queries are queued, tile by tile in chunks of
+// `per` consecutive slots (the tile and the chunk's first slot, in the key and
+// rank buffers, which are free after the grid build), and a spill kernel after
+// the stage spreads the chunks over every workgroup of the GPU. Each tile is a
+// core tile of one region, and a chunk holds at least one hit, so there are at
+// most n chunks.
+__device__ __forceinline__ void spill_region(const Geom& g, const Arena& a, const Region& R, int counter, int per) {
   const int64_t ubase = (int64_t)R.unit * g.tpl;
-  const int nq = L.core_lo[R.ch];
-  for (int q = threadIdx.x; q < nq; q += kWG) {
-    int row, p;
-    core_query(L, R, q, row, p);
-    const int slot = slot_of(L, row, p);
-    const float rho = density_global<K>(g, a, ubase, a.xs[slot], a.ys[slot]);
+  for (int k = threadIdx.x; k < R.cw * R.ch; k += kWG) {
+    const int cy = k / R.cw, cx = k - cy * R.cw;
+    const int64_t t = ubase + (int64_t)(R.ry0 + R.cy0 + cy) * g.nx + R.rx0 + R.cx0 + cx;
+    const int s0 = a.tile_start[t], s1 = a.tile_start[t + 1];
+    const int nch = (s1 - s0 + per - 1) / per;
+    if (nch == 0) continue;
+    const int i0 = atomicAdd(&a.counters[counter], nch);
+    for (int c = 0; c < nch; ++c) {
+      a.key[i0 + c] = (int)t;
+      a.rank[i0 + c] = s0 + c * per;
+    }
+  }
+}
+
+// Density of the spilled queries, one lane per query, from global memory.
+template <bool G, int K>
+__global__ __launch_bounds__(kWG) void k_density_spill(DescArg<G> dg, Geom g, Arena a) {
+  const int nch = a.counters[C_SPILL_RHO];
+  const bool keep = g.flags & 2u;
+  for (int i = blockIdx.x; i < nch; i += gridDim.x) {
+    const int64_t t = a.key[i];
+    const int slot = a.rank[i] + (int)threadIdx.x;
+    if (slot >= a.tile_start[t + 1]) continue;
+    const float rho = density_global<K>(g, a, t - t % g.tpl, a.xs[slot], a.ys[slot]);
     a.rho[slot] = rho;
     if (keep) a.rho_out[a.hs[slot]] = rho;
   }
@@ -1278,7 +1305,7 @@ __global__ __launch_bounds__(kWG, density_min_waves(MAXL, K)) void k_density(Des
             if (R.total <= g.lds_cap)
               density_staged<MAXL, K>(g, a, R, L, rec, stile, qidx, keep);
             else
-              density_global_region<K>(g, a, R, L, keep);
+              spill_region(g, a, R, C_SPILL_RHO, kWG);
           }
       }
   }
@@ -1575,7 +1602,7 @@ __device__ __forceinline__ void nh_item(const Geom& g, const Arena& a, const Run
   const int ev_first = event_first_hit(a, d, R.e);
   if (event_first_hit(a, d, R.e + 1) - ev_first > kPackedEventMax) {
     // an event too large for the packed index word takes the global-memory path
-    nh_global_region<STRICT>(g, a, d, R, L, ev_first);
+    spill_region(g, a, R, C_SPILL_NH, kWG / g.tpq);
     return;
   }
   if (R.total <= g.lds_cap) {
@@ -1600,10 +1627,42 @@ __device__ __forceinline__ void nh_item(const Geom& g, const Arena& a, const Run
           make_region(g, unit, tx, ty, tx, ty, R);
           region_setup(g, a, R, L);
           if (L.core_lo[R.ch] == 0) continue;
-          if (!(R.total <= g.lds_cap && nh_staged<STRICT>(g, a, d, R, L, rec, queue, s_qn, ev_first)))
+          if (R.total > g.lds_cap)
+            spill_region(g, a, R, C_SPILL_NH, kWG / g.tpq);
+          else if (!nh_staged<STRICT>(g, a, d, R, L, rec, queue, s_qn, ev_first))
             nh_global_region<STRICT>(g, a, d, R, L, ev_first);
         }
     }
+}
+
+// Nearest-higher of the spilled queries, tpq lanes per query, from global
+// memory, with the decision.
+template <bool G, bool STRICT>
+__global__ __launch_bounds__(kWG) void k_nh_spill(DescArg<G> dg, Geom g, Arena a) {
+  const RunDesc d = dg.get();
+  const int nch = a.counters[C_SPILL_NH];
+  const int tpq = g.tpq;
+  const int sub = threadIdx.x & (tpq - 1);
+  for (int i = blockIdx.x; i < nch; i += gridDim.x) {  // uniform per workgroup: the shuffles below
+    const int64_t t = a.key[i];
+    const int slot = a.rank[i] + (int)threadIdx.x / tpq;
+    const bool active = slot < a.tile_start[t + 1];
+    const int64_t ubase = t - t % g.tpl;
+    const int ev_first = event_first_hit(a, d, (int)(t / ((int64_t)g.L * g.tpl)));
+    NhBest b = nh_start(g.dm2);
+    unsigned hi = 0;
+    if (active) {
+      const float xi = a.xs[slot], yi = a.ys[slot];
+      hi = (unsigned)a.hs[slot];
+      const Window W = query_window(g, g.win_dm, xi, yi);
+      nh_global_scan<STRICT>(g, a, ubase, W, sub, tpq, xi, yi, ord_f32(a.rho[slot]), hi, b);
+    }
+    nh_reduce(b, tpq);
+    if (active && sub == 0) {
+      if (b.p <= -2) b.p = -2 - b.p;
+      decide_and_store(g, a, d, slot, (int)hi, a.rho[slot], b, ev_first);
+    }
+  }
 }
 
 // Built for eight waves per SIMD (64 VGPRs): the compiler then keeps one
@@ -1946,6 +2005,9 @@ static hipError_t launch_all(const Geom& g, const Arena& a, DescArg<G> dg, const
   const int g_rho = G ? cfg.persist_blocks_rho : (int)std::max<int64_t>(1, items);
   const int g_nh = G ? cfg.persist_blocks_nh : (int)std::max<int64_t>(1, items);
   const int g_scan_t = G ? cfg.persist_blocks_scan : cdiv(tt, kScanChunk);
+  // spill kernels: one workgroup per CU in single launches (an empty queue
+  // costs one counter read per workgroup)
+  const int g_spill = G ? cfg.persist_blocks_stream : 256;
   const int g_scan_s = G ? cfg.persist_blocks_scan : cdiv(n + 1, kScanChunk);
   const bool fol = !(g.flags & 8u);
   int k = 0;
@@ -1969,22 +2031,28 @@ static hipError_t launch_all(const Geom& g, const Arena& a, DescArg<G> dg, const
       k_density<G, 2, 0><<<g_rho, kWG, lds, s>>>(dg, g, a);
     else
       k_density<G, 3, 0><<<g_rho, kWG, lds, s>>>(dg, g, a);
+    k_density_spill<G, 0><<<g_spill, kWG, 0, s>>>(dg, g, a);
   } else if (g.kernel == 1) {
     if (g.maxl == 2)
       k_density<G, 2, 1><<<g_rho, kWG, lds, s>>>(dg, g, a);
     else
       k_density<G, 3, 1><<<g_rho, kWG, lds, s>>>(dg, g, a);
+    k_density_spill<G, 1><<<g_spill, kWG, 0, s>>>(dg, g, a);
   } else {
     if (g.maxl == 2)
       k_density<G, 2, 2><<<g_rho, kWG, lds, s>>>(dg, g, a);
     else
       k_density<G, 3, 2><<<g_rho, kWG, lds, s>>>(dg, g, a);
+    k_density_spill<G, 2><<<g_spill, kWG, 0, s>>>(dg, g, a);
   }
   mark();
-  if (g.flags & 4u)
+  if (g.flags & 4u) {
     k_nearest_higher<G, true><<<g_nh, kWG, lds_bytes_nh(g), s>>>(dg, g, a);
-  else
+    k_nh_spill<G, true><<<g_spill, kWG, 0, s>>>(dg, g, a);
+  } else {
     k_nearest_higher<G, false><<<g_nh, kWG, lds_bytes_nh(g), s>>>(dg, g, a);
+    k_nh_spill<G, false><<<g_spill, kWG, 0, s>>>(dg, g, a);
+  }
   mark();
   if (builds_lists(g))
     k_scan<G, SCAN_SEEDS_FOLLOW><<<g_scan_s, kWG, 0, s>>>(dg, g, a);
