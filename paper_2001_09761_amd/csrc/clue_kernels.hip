@@ -104,6 +104,21 @@ __device__ __forceinline__ int seed_rank(const Arena& a, int h) {
   return a.seed_wrank[h >> 5] + __popc(a.seedbits[h >> 5] & ((1u << (h & 31)) - 1u));
 }
 
+// Event of tile-CSR slot s: slots are ordered by (event, layer, tile), so the
+// event is the last e whose first tile starts at or before s.
+__device__ __forceinline__ int event_of_slot(const Geom& g, const Arena& a, const RunDesc& d, int s) {
+  const int64_t per = (int64_t)g.L * g.tpl;
+  int lo = 0, hi = d.n_events - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (a.tile_start[mid * per] <= s)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
 // ---------------------------------------------------------------------------
 // Streaming kernels cut their index range into chunks of `chunk` consecutive
 // indices and give each XCD one contiguous run of chunks (workgroups are
@@ -1703,8 +1718,15 @@ __global__ __launch_bounds__(kWG) void k_label(DescArg<G> dg, Geom g, Arena a) {
   __shared__ int s_par[C];
   __shared__ int s_hs[C];
   __shared__ unsigned char s_fl[C];
+  __shared__ int s_ev[2];  // the chunk's event when it holds one event (else -1), its first hit
   for (ChunkRun rn = xcd_run(d.n, C); rn.c < rn.end; rn.c += rn.step) {
     const int c0 = rn.c * C;
+    if (threadIdx.x == 0) {
+      const int e0 = event_of_slot(g, a, d, c0);
+      const int e1 = event_of_slot(g, a, d, min(c0 + C, d.n) - 1);
+      s_ev[0] = e0 == e1 ? e0 : -1;
+      s_ev[1] = event_first_hit(a, d, e0);
+    }
     const int sb = c0 + (int)threadIdx.x;
     int s[U], p0[U], hsj[U], r[U], p[U];
     unsigned f[U];
@@ -1727,12 +1749,20 @@ __global__ __launch_bounds__(kWG) void k_label(DescArg<G> dg, Geom g, Arena a) {
     }
     __syncthreads();
     auto staged = [&](int x) { return (unsigned)(x - c0) < (unsigned)C; };
+    // first hit of each hit's event, from its slot
+    const int ev1 = s_ev[0], first1 = s_ev[1];
+    int first[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j)
+      first[j] = ev1 >= 0 || !v[j] ? first1 : event_first_hit(a, d, event_of_slot(g, a, d, s[j]));
     if (fol) {
+      // entries are event-local already: the list sort then leaves lists of
+      // one entry alone
 #pragma unroll
       for (int j = 0; j < U; ++j) {
         if (v[j] && (f[j] & F_FOLLOWER)) {
           const int owner = staged(p0[j]) ? s_hs[p0[j] - c0] : a.hs[p0[j]];
-          a.flist[a.fstart[owner] + a.frank[s[j]]] = hsj[j];
+          a.flist[a.fstart[owner] + a.frank[s[j]]] = hsj[j] - first[j];
         }
       }
     }
@@ -1759,10 +1789,8 @@ __global__ __launch_bounds__(kWG) void k_label(DescArg<G> dg, Geom g, Arena a) {
       if (r[j] != s[j] && r[j] != p0[j]) st_relaxed(&a.parent[s[j]], r[j]);
       const bool in = staged(r[j]);
       int lab = -1;
-      if ((in ? s_fl[r[j] - c0] : a.flags[r[j]]) & F_SEED) {
-        const int e = d.event ? clampi(d.event[hsj[j]] - d.event_base, 0, d.n_events - 1) : 0;
-        lab = seed_rank(a, in ? s_hs[r[j] - c0] : a.hs[r[j]]) - seed_rank(a, event_first_hit(a, d, e));
-      }
+      if ((in ? s_fl[r[j] - c0] : a.flags[r[j]]) & F_SEED)
+        lab = seed_rank(a, in ? s_hs[r[j] - c0] : a.hs[r[j]]) - seed_rank(a, first[j]);
       d.cluster_id[hsj[j]] = lab;
     }
     __syncthreads();  // the next chunk overwrites the staged arrays
@@ -1871,8 +1899,10 @@ __global__ __launch_bounds__(kWG) void k_expand_dfs(DescArg<G> dg, Geom g, Arena
   }
 }
 
-// Follower lists: sort each list by hit index, then make indices event-local.
-// Lists of up to kShortList entries are sorted in registers (odd-even
+// Follower lists: sort each list by hit index. k_label writes event-local
+// entries, so lists of one entry are already final; after the depth-first
+// expansion (which walks caller indices) every entry is made event-local
+// here. Lists of up to kShortList entries are sorted in registers (odd-even
 // transposition networks of four entries, when every list of the wave fits,
 // or eight); longer ones by insertion in place.
 constexpr int kShortList = 8;
@@ -1900,10 +1930,12 @@ __global__ __launch_bounds__(kWG) void k_follow_sort(DescArg<G> dg, Geom g, Aren
       // nearly every wave holds only lists of up to four entries: then the
       // whole wave takes the shorter network (a wave-uniform choice)
       const bool four = __all(len <= 4);
-      if (len == 0) continue;
-      const int h = hb + j * kWG;
-      const int e = d.event ? clampi(d.event[h] - d.event_base, 0, d.n_events - 1) : 0;
-      const int off = event_first_hit(a, d, e);
+      if (len < (g.expand ? 1 : 2)) continue;
+      int off = 0;
+      if (g.expand) {
+        const int h = hb + j * kWG;
+        off = event_first_hit(a, d, d.event ? clampi(d.event[h] - d.event_base, 0, d.n_events - 1) : 0);
+      }
       if (four) {
         int v[4];
 #pragma unroll
