@@ -204,14 +204,17 @@ __global__ __launch_bounds__(kWG) void k_hist(DescArg<G> dg, Geom g, Arena a) {
       unsigned long long todo = __ballot(valid);
       int ld = lane, o = 0, cnt = 0;
       while (todo) {  // wave-uniform: one pass per distinct tile in the wave
+        // the lowest unmatched lane leads; its tile is read into a scalar
+        // register, and a lane's offset is the count of its peers below it
         const int l = __ffsll((long long)todo) - 1;
-        const int lt = __shfl(t[j], l, 64);
-        const unsigned long long peers = __ballot(t[j] == lt) & todo;
-        if ((peers >> lane) & 1ull) {
+        const int lt = __builtin_amdgcn_readlane(t[j], l);
+        const bool mine = t[j] == lt;  // invalid lanes (-1) never match a tile
+        const unsigned long long peers = __ballot(mine);
+        if (mine) {
           ld = l;
-          o = __popcll(peers & ((1ull << lane) - 1ull));
+          o = __builtin_amdgcn_mbcnt_hi((unsigned)(peers >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)peers, 0u));
+          cnt = __popcll(peers);
         }
-        if (lane == l) cnt = __popcll(peers);
         todo &= ~peers;
       }
       base[j] = 0;
