@@ -649,12 +649,17 @@ __device__ __forceinline__ int region_row_of(const RegionLds& L, int rh, int p) 
   return lo;
 }
 
-// Core query q -> (region row, LDS position).
-__device__ __forceinline__ void core_query(const RegionLds& L, const Region& R, int q, int& row, int& p) {
-  int cr = 0;
+// Core query q -> (region row, LDS position). `cr` is a core row at or
+// before q's, and is left at q's: a lane walking its queries in increasing
+// order keeps it between calls.
+__device__ __forceinline__ void core_query(const RegionLds& L, const Region& R, int q, int& cr, int& row, int& p) {
   while (cr + 1 < R.ch && L.core_lo[cr + 1] <= q) ++cr;
   row = R.cy0 + cr;
   p = L.ts[row * (R.rw + 1) + R.cx0] + (q - L.core_lo[cr]);
+}
+__device__ __forceinline__ void core_query(const RegionLds& L, const Region& R, int q, int& row, int& p) {
+  int cr = 0;
+  core_query(L, R, q, cr, row, p);
 }
 
 __device__ __forceinline__ int slot_of(const RegionLds& L, int row, int p) { return L.row_gs[row] + (p - L.row_lo[row]); }
@@ -1043,7 +1048,7 @@ __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, co
         }
         const int incl = wave_incl_scan(len, threadIdx.x);
         if (q < nquad) L.qoff[q] = run + incl - len;
-        run += __shfl(incl, 63, 64);
+        run += __builtin_amdgcn_readlane(incl, 63);
       }
       if (threadIdx.x == 0) {
         L.qoff[nquad] = run;
@@ -1172,9 +1177,10 @@ __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, co
     use_quads = false;
   }
   const int nq = L.core_lo[R.ch];
+  int cr = 0;
   for (int q = threadIdx.x; q < nq; q += kWG) {
     int row, p;
-    core_query(L, R, q, row, p);
+    core_query(L, R, q, cr, row, p);
     const int slot = slot_of(L, row, p);
     const float4 me = rec[p];
     const float xi = me.x, yi = me.y;
@@ -1510,11 +1516,12 @@ __device__ __forceinline__ bool nh_staged(const Geom& g, const Arena& a, const R
   if (__syncthreads_or(outside)) return false;
   const int nq = L.core_lo[R.ch];
   // phase 1: radius r1; only hits strictly within r1 can settle a query here
+  int cr = 0;
   for (int q = threadIdx.x; q < nq; q += kWG) {
     bool done = false;
     if (g.nh_phase1) {
       int row, p;
-      core_query(L, R, q, row, p);
+      core_query(L, R, q, cr, row, p);
       const float4 me = rec[p];
       const unsigned ordi = __float_as_uint(me.w), zi = __float_as_uint(me.z);
       const Window W = query_window(g, g.win_r1, me.x, me.y);
@@ -1585,6 +1592,7 @@ __device__ __forceinline__ void nh_global_region(const Geom& g, const Arena& a, 
   const int tpq = g.tpq;
   const int sub = threadIdx.x & (tpq - 1);
   const int qpp = kWG / tpq;
+  int cr = 0;
   for (int base = 0; base < nq; base += qpp) {
     const int q = base + threadIdx.x / tpq;
     const bool active = q < nq;
@@ -1593,7 +1601,7 @@ __device__ __forceinline__ void nh_global_region(const Geom& g, const Arena& a, 
     unsigned hi = 0;
     if (active) {
       int row, p;
-      core_query(L, R, q, row, p);
+      core_query(L, R, q, cr, row, p);
       slot = slot_of(L, row, p);
       const float xi = a.xs[slot], yi = a.ys[slot];
       hi = (unsigned)a.hs[slot];
