@@ -20,6 +20,10 @@ constexpr int kMaxLdsCap = 2048;
 // Bytes of the density kernel's per-hit LDS arrays (float4 record, 16-bit
 // tile id, four 16-bit quad entries), rounded up to 16.
 __host__ __device__ constexpr int lds_records_density(int lds_cap) { return (lds_cap * (16 + 2 + 8) + 15) & ~15; }
+// ... and of the nearest-higher kernel's (float4 record, 16-bit queue entry,
+// 8-bit region row).
+__host__ __device__ constexpr int lds_records_nh(int lds_cap) { return (lds_cap * (16 + 2 + 1) + 15) & ~15; }
+static_assert(kMaxLdsCap <= 65536, "nearest-higher queue entries are 16-bit");
 constexpr int kStagePer = 4;       // staged hits per lane per round (loads in flight)
 constexpr int kPlaceU = 4;         // hits per lane per step of the streaming grid-build and list kernels
 constexpr int kBatchU = 8;         // ... and of the batched k_scatter, k_place and k_label: longer runs

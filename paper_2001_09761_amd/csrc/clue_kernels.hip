@@ -1484,18 +1484,21 @@ __device__ __forceinline__ void nh_global_scan(const Geom& g, const Arena& a, in
 // global memory.
 template <bool STRICT>
 __device__ __forceinline__ bool nh_staged(const Geom& g, const Arena& a, const RunDesc& d, const Region& R, const RegionLds& L,
-                          float4* rec, int* queue, int* s_qn, int ev_first) {
+                          float4* rec, unsigned short* queue, unsigned char* prow, int* s_qn, int ev_first) {
   const int per_row = R.rw + 1;
   const int64_t ubase = (int64_t)R.unit * g.tpl;
-  // every global load of a lane is issued before its first LDS store
+  // every global load of a lane is issued before its first LDS store; the
+  // region row of each staged position is kept for the winners' slots
   bool outside = false;  // a hit whose event-local index does not fit the packed word
   for (int base = 0; base < R.total; base += kStagePer * kWG) {
     float4 v[kStagePer];
+    int rw[kStagePer];
 #pragma unroll
     for (int k = 0; k < kStagePer; ++k) {
       const int p = base + (int)threadIdx.x + k * kWG;
       if (p < R.total) {
-        const int s = slot_of(L, region_row_of(L, R.rh, p), p);
+        rw[k] = region_row_of(L, R.rh, p);
+        const int s = slot_of(L, rw[k], p);
         v[k] = make_float4(a.xs[s], a.ys[s], a.rho[s], __int_as_float(a.hs[s]));
       }
     }
@@ -1506,6 +1509,7 @@ __device__ __forceinline__ bool nh_staged(const Geom& g, const Arena& a, const R
         outside |= (unsigned)(__float_as_int(v[k].w) - ev_first) >= (unsigned)kPackedEventMax;
         rec[p] = make_float4(v[k].x, v[k].y, __uint_as_float(nh_pack(__float_as_int(v[k].w), ev_first, p)),
                              __uint_as_float(ord_f32(v[k].z)));
+        prow[p] = (unsigned char)rw[k];
       }
     }
   }
@@ -1532,13 +1536,13 @@ __device__ __forceinline__ bool nh_staged(const Geom& g, const Arena& a, const R
         nh_scan_staged<STRICT>(rec, L.ts, per_row, tx0, tx1, ty0, ty1, 0, 1, me.x, me.y, ordi, zi, b);
         nh_unpack(b, k0, ev_first);
         if (b.p >= 0) {
-          b.p = slot_of(L, region_row_of(L, R.rh, b.p), b.p);
+          b.p = slot_of(L, prow[b.p], b.p);
           decide_and_store(g, a, d, slot_of(L, row, p), nh_unpack_h(zi, ev_first), ord_inv(ordi), b, ev_first);
           done = true;
         }
       }
     }
-    if (!done) queue[atomicAdd(s_qn, 1)] = q;
+    if (!done) queue[atomicAdd(s_qn, 1)] = (unsigned short)q;
   }
   __syncthreads();
   // phase 2: full d_m window, tpq lanes per query
@@ -1575,7 +1579,7 @@ __device__ __forceinline__ bool nh_staged(const Geom& g, const Arena& a, const R
     nh_unpack(b, k0, ev_first);
     if (active && sub == 0) {
       if (b.p >= 0)
-        b.p = slot_of(L, region_row_of(L, R.rh, b.p), b.p);
+        b.p = slot_of(L, prow[b.p], b.p);
       else if (b.p <= -2)
         b.p = -2 - b.p;
       decide_and_store(g, a, d, slot, (int)hi, ord_inv(ordi), b, ev_first);
@@ -1618,7 +1622,7 @@ __device__ __forceinline__ void nh_global_region(const Geom& g, const Arena& a, 
 
 template <bool STRICT>
 __device__ __forceinline__ void nh_item(const Geom& g, const Arena& a, const RunDesc& d, int item, RegionLds& L,
-                                        float4* rec, int* queue, int* s_qn) {
+                                        float4* rec, unsigned short* queue, unsigned char* prow, int* s_qn) {
   int unit, tx0, ty0, tx1, ty1;
   item_block(g, item, unit, tx0, ty0, tx1, ty1);
   Region R;
@@ -1632,7 +1636,7 @@ __device__ __forceinline__ void nh_item(const Geom& g, const Arena& a, const Run
     return;
   }
   if (R.total <= g.lds_cap) {
-    if (!nh_staged<STRICT>(g, a, d, R, L, rec, queue, s_qn, ev_first)) nh_global_region<STRICT>(g, a, d, R, L, ev_first);
+    if (!nh_staged<STRICT>(g, a, d, R, L, rec, queue, prow, s_qn, ev_first)) nh_global_region<STRICT>(g, a, d, R, L, ev_first);
     return;
   }
   // too dense: the four quarter blocks, then single tiles
@@ -1643,7 +1647,7 @@ __device__ __forceinline__ void nh_item(const Geom& g, const Arena& a, const Run
       make_region(g, unit, sx, sy, ex, ey, R);
       region_setup(g, a, R, L);
       if (L.core_lo[R.ch] == 0) continue;
-      if (R.total <= g.lds_cap && nh_staged<STRICT>(g, a, d, R, L, rec, queue, s_qn, ev_first)) continue;
+      if (R.total <= g.lds_cap && nh_staged<STRICT>(g, a, d, R, L, rec, queue, prow, s_qn, ev_first)) continue;
       if (R.total <= g.lds_cap) {
         nh_global_region<STRICT>(g, a, d, R, L, ev_first);
         continue;
@@ -1655,7 +1659,7 @@ __device__ __forceinline__ void nh_item(const Geom& g, const Arena& a, const Run
           if (L.core_lo[R.ch] == 0) continue;
           if (R.total > g.lds_cap)
             spill_region(g, a, R, C_SPILL_NH, kWG / g.tpq);
-          else if (!nh_staged<STRICT>(g, a, d, R, L, rec, queue, s_qn, ev_first))
+          else if (!nh_staged<STRICT>(g, a, d, R, L, rec, queue, prow, s_qn, ev_first))
             nh_global_region<STRICT>(g, a, d, R, L, ev_first);
         }
     }
@@ -1702,12 +1706,13 @@ __global__ __launch_bounds__(kWG, 8) void k_nearest_higher(DescArg<G> dg, Geom g
   __shared__ int s_qn;
   __shared__ int s_item;
   float4* rec = reinterpret_cast<float4*>(smem);
-  int* queue = reinterpret_cast<int*>(rec + g.lds_cap);
-  RegionLds L = region_lds(s_rows, queue + g.lds_cap, nullptr);
+  unsigned short* queue = reinterpret_cast<unsigned short*>(rec + g.lds_cap);
+  unsigned char* prow = reinterpret_cast<unsigned char*>(queue + g.lds_cap);
+  RegionLds L = region_lds(s_rows, reinterpret_cast<int*>(smem + lds_records_nh(g.lds_cap)), nullptr);
   const int n_items = d.n_events * g.L * g.bpu;
   ItemSched st{0, G ? xcc_id() : 0};
   for (int item; (item = next_item<G>(st, n_items, &a.counters[C_QUEUE_NH], &s_item)) >= 0;)
-    nh_item<STRICT>(g, a, d, item, L, rec, queue, &s_qn);
+    nh_item<STRICT>(g, a, d, item, L, rec, queue, prow, &s_qn);
 }
 
 // ---------------------------------------------------------------------------
@@ -2023,9 +2028,9 @@ __global__ void k_set_desc(RunDesc d, RunDesc* dd) {
 // tile id and four 16-bit quad-list entries, then the region's tile offsets
 // and quad-list offsets.
 int lds_bytes_for(const Geom& g) { return lds_records_density(g.lds_cap) + 4 * (g.ts_ints + g.q_ints); }
-// Nearest-higher: per staged hit a float4 record and one queue int, then the
-// region's tile offsets.
-int lds_bytes_nh(const Geom& g) { return g.lds_cap * (16 + 4) + 4 * g.ts_ints; }
+// Nearest-higher: per staged hit a float4 record, a 16-bit queue entry and its
+// region row (a byte), then the region's tile offsets.
+int lds_bytes_nh(const Geom& g) { return lds_records_nh(g.lds_cap) + 4 * g.ts_ints; }
 
 static inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
