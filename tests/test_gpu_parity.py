@@ -308,6 +308,31 @@ def test_decreasing_event_ids_without_validation():
     assert_parity(got, _ref(good, p), where="valid batch after decreasing ids")
 
 
+@pytest.mark.parametrize("tuning", [None, dict(threads_per_query=1), dict(threads_per_query=8)])
+def test_dense_cores_in_a_batch_go_through_the_spill_kernels(tuning):
+    """Three events in one batched run (graph form): two hold a core of 1500
+    hits in one tile next to sparse hits, so the density and nearest-higher
+    stages queue those tiles' queries for the spill kernels (chunks of 256
+    and of 256 / tpq queries, several per tile, from two events and several
+    layers); the third event stays on the staged path. Every output equals
+    the oracle's."""
+    rng = np.random.default_rng(11)
+    evs = []
+    for e in range(3):
+        x = rng.uniform(0, 20, 400).astype(np.float32)
+        y = rng.uniform(0, 20, 400).astype(np.float32)
+        layer = rng.integers(0, 3, 400).astype(np.int32)
+        if e != 1:
+            for L in (0, 2):
+                x = np.concatenate([x, rng.normal(5.0 + 3 * e, 0.3, 1500).astype(np.float32)])
+                y = np.concatenate([y, rng.normal(12.0, 0.3, 1500).astype(np.float32)])
+                layer = np.concatenate([layer, np.full(1500, L, np.int32)])
+        evs.append(dict(x=x, y=y, layer=layer, energy=rng.uniform(0.1, 1.0, x.size).astype(np.float32)))
+    b = gen.concat_events(evs)
+    print(f"dense cores in a batch: {b['x'].size} hits, tuning {tuning}", flush=True)
+    assert_parity(gpu_run(b, ADV_P, batched=True, n_events=3, tuning=tuning), _ref(b, ADV_P), where="dense batch")
+
+
 def test_dense_core_takes_the_global_merge_and_scales():
     """A core far denser than any LDS cap: m hits inside one tile, all within
     dc of one another, so every query has about m neighbours and exact
