@@ -207,7 +207,9 @@ typedef struct {
   int32_t block_x, block_y; /* tiles per work item (1..16 each) */
   int32_t lds_cap;          /* hits staged in LDS per work item (64..2048, default
                                960); denser items are split into quarter blocks,
-                               then single tiles, then use global memory */
+                               then single tiles; a tile still too dense is
+                               searched in global memory by a follow-up kernel
+                               that spreads its queries over the whole GPU */
   float nh_first_radius;    /* radius (cm) of the first nearest-higher pass; a hit
                                whose nearest-higher lies strictly inside it skips
                                the full d_m search. 0 or >= d_m: single pass */
