@@ -533,8 +533,8 @@ __global__ __launch_bounds__(kWG) void k_scan(DescArg<G> dg, Geom g, Arena a) {
 // bx*by tiles (the core); its staged region adds `halo` tiles around the core
 // (clamped to the grid). Dense blocks whose region does not fit in LDS are
 // processed as four quarter blocks, a quarter that still does not fit one
-// core tile at a time, and a tile whose own region does not fit falls back
-// to global memory.
+// core tile at a time, and a tile whose own region does not fit is queued
+// for the stage's spill kernel, which searches global memory.
 // ---------------------------------------------------------------------------
 struct Region {
   int unit;       // event * L + layer
@@ -1631,7 +1631,8 @@ __device__ __forceinline__ void nh_item(const Geom& g, const Arena& a, const Run
   if (L.core_lo[R.ch] == 0) return;
   const int ev_first = event_first_hit(a, d, R.e);
   if (event_first_hit(a, d, R.e + 1) - ev_first > kPackedEventMax) {
-    // an event too large for the packed index word takes the global-memory path
+    // an event too large for the packed index word: the spill kernel searches
+    // global memory, where records carry caller indices
     spill_region(g, a, R, C_SPILL_NH, kWG / g.tpq);
     return;
   }
