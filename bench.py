@@ -53,9 +53,23 @@ CLOCK_GHZ = 2.4
 VALU_ISSUE_CEILING = 1.0  # wave64 VALU instructions per CU-cycle
 
 
+def code_sha(sources) -> str:
+    """Hash of C/C++ sources with comments and blank space removed (the
+    sources hold no string literal with a comment marker)."""
+    import re
+    h = hashlib.sha256()
+    for src in sources:
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
+    return h.hexdigest()[:16]
+
+
 def kernel_source_sha() -> str:
-    p = os.path.join(ROOT, "paper_2001_09761_amd", "csrc", "clue_kernels.hip")
-    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+    """Code hash of the kernel source and the internal header it includes:
+    profiles stay valid across edits that change no code."""
+    return code_sha(open(os.path.join(ROOT, "paper_2001_09761_amd", "csrc", f)).read()
+                    for f in ("clue_kernels.hip", "clue_internal.h"))
 
 
 def percentile(v, q):

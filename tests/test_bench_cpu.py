@@ -97,6 +97,13 @@ def test_linear_fit_recovers_a_line():
     assert f["r2"] == pytest.approx(1.0)
 
 
+def test_code_sha_ignores_comments_and_spacing_only():
+    a = "int f(int x) {\n  return x + 1;  // one more\n}\n"
+    b = "/* header */ int f(int x) { return x + 1; }"
+    c = "int f(int x) { return x + 2; }"
+    assert bench.code_sha([a]) == bench.code_sha([b]) != bench.code_sha([c])
+
+
 def test_tuning_kwargs():
     t = {"block": (10, 8), "tile_size": 4.0, "lds_cap": 768, "plain_lds_cap": 960, "ms": 4.8, "density_quads": 1}
     kw = bench.tuning_kwargs(t)
