@@ -1774,14 +1774,20 @@ __global__ __launch_bounds__(kWG) void k_label(DescArg<G> dg, Geom g, Arena a) {
       first[j] = ev1 >= 0 || !v[j] ? first1 : event_first_hit(a, d, event_of_slot(g, a, d, s[j]));
     if (fol) {
       // entries are event-local already: the list sort then leaves lists of
-      // one entry alone
+      // one entry alone. Every load of a lane comes before its first store
+      // (the stores could alias them as far as the compiler knows).
+      int at[U];
 #pragma unroll
       for (int j = 0; j < U; ++j) {
+        at[j] = -1;
         if (v[j] && (f[j] & F_FOLLOWER)) {
           const int owner = staged(p0[j]) ? s_hs[p0[j] - c0] : a.hs[p0[j]];
-          a.flist[a.fstart[owner] + a.frank[s[j]]] = hsj[j] - first[j];
+          at[j] = a.fstart[owner] + a.frank[s[j]];
         }
       }
+#pragma unroll
+      for (int j = 0; j < U; ++j)
+        if (at[j] >= 0) a.flist[at[j]] = hsj[j] - first[j];
     }
 #pragma unroll
     for (int j = 0; j < U; ++j) {
@@ -1800,15 +1806,20 @@ __global__ __launch_bounds__(kWG) void k_label(DescArg<G> dg, Geom g, Arena a) {
       }
       if (!more) break;
     }
+    int lab[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      lab[j] = -1;
+      if (!v[j]) continue;
+      const bool in = staged(r[j]);
+      if ((in ? s_fl[r[j] - c0] : a.flags[r[j]]) & F_SEED)
+        lab[j] = seed_rank(a, in ? s_hs[r[j] - c0] : a.hs[r[j]]) - seed_rank(a, first[j]);
+    }
 #pragma unroll
     for (int j = 0; j < U; ++j) {
       if (!v[j]) continue;
       if (r[j] != s[j] && r[j] != p0[j]) st_relaxed(&a.parent[s[j]], r[j]);
-      const bool in = staged(r[j]);
-      int lab = -1;
-      if ((in ? s_fl[r[j] - c0] : a.flags[r[j]]) & F_SEED)
-        lab = seed_rank(a, in ? s_hs[r[j] - c0] : a.hs[r[j]]) - seed_rank(a, first[j]);
-      d.cluster_id[hsj[j]] = lab;
+      d.cluster_id[hsj[j]] = lab[j];
     }
     __syncthreads();  // the next chunk overwrites the staged arrays
   }
