@@ -174,27 +174,38 @@ __global__ __launch_bounds__(kWG) void k_hist(DescArg<G> dg, Geom g, Arena a) {
   const int lane = threadIdx.x & 63;
   for (ChunkRun r = xcd_run(d.n, kWG * U); r.c < r.end; r.c += r.step) {
     const int h0 = r.c * kWG * U;  // uniform per workgroup
-    int t[U];
+    // every load of a lane is issued before its first store (the event
+    // starts below could alias the inputs as far as the compiler knows)
+    int t[U], ev[U], evp[U];
 #pragma unroll
     for (int j = 0; j < U; ++j) {
       const int h = h0 + j * kWG + (int)threadIdx.x;
       t[j] = -1;
+      ev[j] = evp[j] = 0;
       if (h < d.n) {
-        int e = 0;
         if (d.event) {
-          e = clampi(d.event[h] - d.event_base, 0, d.n_events - 1);
-          const int prev = h == 0 ? -1 : clampi(d.event[h - 1] - d.event_base, 0, d.n_events - 1);
-          for (int k = prev + 1; k <= e; ++k) a.ev_start[k] = h;
-          if (h == d.n - 1)
-            for (int k = e + 1; k <= d.n_events; ++k) a.ev_start[k] = d.n;
-        } else if (h == 0) {
-          a.ev_start[0] = 0;
-          a.ev_start[1] = d.n;
+          ev[j] = clampi(d.event[h] - d.event_base, 0, d.n_events - 1);
+          evp[j] = h == 0 ? -1 : clampi(d.event[h - 1] - d.event_base, 0, d.n_events - 1);
         }
         const int l = clampi(d.layer[h], 0, g.L - 1);
         const int tx = tile_coord(d.x[h], g.x0, g.inv_t, g.nx);
         const int ty = tile_coord(d.y[h], g.y0, g.inv_t, g.ny);
-        t[j] = (e * g.L + l) * g.tpl + ty * g.nx + tx;
+        t[j] = l * g.tpl + ty * g.nx + tx;  // the event's part is added below
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      const int h = h0 + j * kWG + (int)threadIdx.x;
+      if (h >= d.n) continue;
+      const int e = ev[j];
+      t[j] += e * g.L * g.tpl;
+      if (d.event) {
+        for (int k = evp[j] + 1; k <= e; ++k) a.ev_start[k] = h;
+        if (h == d.n - 1)
+          for (int k = e + 1; k <= d.n_events; ++k) a.ev_start[k] = d.n;
+      } else if (h == 0) {
+        a.ev_start[0] = 0;
+        a.ev_start[1] = d.n;
       }
     }
     int base[U], off[U], leader[U];
@@ -390,29 +401,18 @@ __global__ __launch_bounds__(kWG) void k_scan(DescArg<G> dg, Geom g, Arena a) {
       // so that the prefix at 32 w counts the seeds before word w
       static_assert(SI % 32 == 0 || 32 % SI == 0, "a thread's elements hold whole words or none");
       const int64_t nw = seed_words(d.n);
+      // the bitmap words of this thread's elements, loaded once
+      constexpr int NW = (SI + 31) / 32;
+      unsigned wv[NW];
+#pragma unroll
+      for (int k = 0; k < NW; ++k) wv[k] = (base >> 5) + k < nw ? a.seedbits[(base >> 5) + k] : 0u;
 #pragma unroll
       for (int i = 0; i < SI; ++i) {
         const int64_t e = base + i;
-        v[0][i] = ((e & 31) == 0 && (e >> 5) < nw) ? __popc(a.seedbits[e >> 5]) : 0;
+        v[0][i] = (e & 31) == 0 ? __popc(wv[(e >> 5) - (base >> 5)]) : 0;
       }
-      // the caller-order seed flags, expanded from the bitmap 16 at a time
-      // (one bit per hit -> one byte per hit), in coalesced stores
-      static_assert(SI % 16 == 0, "flags are written 16 at a time");
-#pragma unroll
-      for (int q = 0; q < SI; q += 16) {
-        const int64_t e0 = base + q;
-        if (e0 >= nel) break;
-        const unsigned w = (a.seedbits[e0 >> 5] >> (e0 & 31)) & 0xffffu;
-        unsigned b4[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) b4[k] = (((w >> (4 * k)) & 0xfu) * 0x00204081u) & 0x01010101u;
-        uint8_t* dst = d.is_seed + e0;
-        if (e0 + 16 <= nel && ((uintptr_t)dst & 15u) == 0) {
-          *reinterpret_cast<uint4*>(dst) = make_uint4(b4[0], b4[1], b4[2], b4[3]);
-        } else {
-          for (int k = 0; k < 16 && e0 + k < nel; ++k) dst[k] = (uint8_t)((w >> k) & 1u);
-        }
-      }
+      // the follower counts are loaded before the flag stores below, which
+      // could alias them as far as the compiler knows
       if constexpr (NCH == 2) {
         if (base + SI <= nel) {
           const int4* p = reinterpret_cast<const int4*>(a.fstart + base);
@@ -424,6 +424,24 @@ __global__ __launch_bounds__(kWG) void k_scan(DescArg<G> dg, Geom g, Arena a) {
         } else {
 #pragma unroll
           for (int i = 0; i < SI; ++i) v[1][i] = base + i < nel ? a.fstart[base + i] : 0;
+        }
+      }
+      // the caller-order seed flags, expanded from the bitmap 16 at a time
+      // (one bit per hit -> one byte per hit), in coalesced stores
+      static_assert(SI % 16 == 0, "flags are written 16 at a time");
+#pragma unroll
+      for (int q = 0; q < SI; q += 16) {
+        const int64_t e0 = base + q;
+        if (e0 >= nel) break;
+        const unsigned w = (wv[(e0 >> 5) - (base >> 5)] >> (e0 & 31)) & 0xffffu;
+        unsigned b4[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) b4[k] = (((w >> (4 * k)) & 0xfu) * 0x00204081u) & 0x01010101u;
+        uint8_t* dst = d.is_seed + e0;
+        if (e0 + 16 <= nel && ((uintptr_t)dst & 15u) == 0) {
+          *reinterpret_cast<uint4*>(dst) = make_uint4(b4[0], b4[1], b4[2], b4[3]);
+        } else {
+          for (int k = 0; k < 16 && e0 + k < nel; ++k) dst[k] = (uint8_t)((w >> k) & 1u);
         }
       }
     }
