@@ -300,28 +300,47 @@ __global__ __launch_bounds__(kWG) void k_place(DescArg<G> dg, Geom g, Arena a) {
       s_ids[sl - c0] = sl < d.n ? ids[sl] : 0;
     }
     __syncthreads();
+    // slots in groups of four: a group's loads are all issued before its
+    // first store (which could alias them as far as the compiler knows)
+    constexpr int V = 4;
 #pragma unroll
-    for (int j = 0; j < U; ++j) {
-      const int sl = c0 + (int)threadIdx.x + j * kWG;
-      if (sl >= d.n) continue;
-      const int h = s_ids[sl - c0];
-      const int t = a.parent[sl];
-      const float x = d.x[h], y = d.y[h], e = d.e[h];
-      const int s0 = a.tile_start[t], s1 = a.tile_start[t + 1];
-      // the tile [s0, s1) in three parts: before the chunk, in it, after it
-      const int m0 = min(max(s0, c0), s1), m1 = max(min(s1, c1), m0);
-      int rk = 0;
-      for (int c = s0; c < m0; ++c) rk += ids[c] < h;
-      int c = m0;
-      for (; c + 3 < m1; c += 4)
-        rk += (s_ids[c - c0] < h) + (s_ids[c + 1 - c0] < h) + (s_ids[c + 2 - c0] < h) + (s_ids[c + 3 - c0] < h);
-      for (; c < m1; ++c) rk += s_ids[c - c0] < h;
-      for (c = m1; c < s1; ++c) rk += ids[c] < h;
-      const int slot = s0 + rk;
-      a.xs[slot] = x;
-      a.ys[slot] = y;
-      a.es[slot] = e;
-      a.hs[slot] = h;
+    for (int j0 = 0; j0 < U; j0 += V) {
+      int hv[V], s0v[V], s1v[V];
+      float xv[V], yv[V], ev[V];
+#pragma unroll
+      for (int k = 0; k < V; ++k) {
+        const int sl = c0 + (int)threadIdx.x + (j0 + k) * kWG;
+        hv[k] = -1;
+        if (sl < d.n) {
+          const int h = s_ids[sl - c0];
+          const int t = a.parent[sl];
+          hv[k] = h;
+          xv[k] = d.x[h];
+          yv[k] = d.y[h];
+          ev[k] = d.e[h];
+          s0v[k] = a.tile_start[t];
+          s1v[k] = a.tile_start[t + 1];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < V; ++k) {
+        if (hv[k] < 0) continue;
+        const int h = hv[k], s0 = s0v[k], s1 = s1v[k];
+        // the tile [s0, s1) in three parts: before the chunk, in it, after it
+        const int m0 = min(max(s0, c0), s1), m1 = max(min(s1, c1), m0);
+        int rk = 0;
+        for (int c = s0; c < m0; ++c) rk += ids[c] < h;
+        int c = m0;
+        for (; c + 3 < m1; c += 4)
+          rk += (s_ids[c - c0] < h) + (s_ids[c + 1 - c0] < h) + (s_ids[c + 2 - c0] < h) + (s_ids[c + 3 - c0] < h);
+        for (; c < m1; ++c) rk += s_ids[c - c0] < h;
+        for (c = m1; c < s1; ++c) rk += ids[c] < h;
+        const int slot = s0 + rk;
+        a.xs[slot] = xv[k];
+        a.ys[slot] = yv[k];
+        a.es[slot] = ev[k];
+        a.hs[slot] = h;
+      }
     }
     __syncthreads();  // the next chunk overwrites the staged ids
   }
