@@ -1021,6 +1021,15 @@ __device__ __forceinline__ float4 rec_at(const float4* rec, int byte_off) {
   return *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(rec) + byte_off);
 }
 static_assert(kMaxLdsCap * 16 <= 65536, "quad-list byte offsets are 16-bit");
+// Byte address of a shared-memory object in the workgroup's LDS, and a load
+// from such an address: loops that step through LDS by byte address then need
+// no base register added per access.
+__device__ __forceinline__ unsigned lds_address(const void* p) {
+  return (unsigned)(size_t)(const __attribute__((address_space(3))) void*)p;
+}
+__device__ __forceinline__ int lds_load_int(unsigned addr) {
+  return *(const __attribute__((address_space(3))) int*)(size_t)addr;
+}
 static_assert(kMaxRegionRows <= 64 && kMaxRegionTiles <= 1024, "a staged tile id is (row << 10) | column in 16 bits");
 
 // Density over a staged region (records x, y, E, index; each tile in
@@ -1173,28 +1182,40 @@ __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, co
             len[k] = L.ts[nt + 1] - lo[k];
           }
         }
-      int below[9];
+      // The searches share one power-of-two step sequence, from the largest
+      // of the tiles down to one record. Each holds the LDS address of its
+      // last counted key (at first, the key before its tile); a step probes
+      // the key `step` records further on, clamped to the tile's last key. A
+      // clamped probe is taken only when every key of the tile is smaller,
+      // which is then the count. So no search branches, and all loads of a
+      // step are issued before its compares. An empty tile starts and ends
+      // at record 0's key, so every probe reads a staged key.
+      int maxlen = 0;
 #pragma unroll
-      for (int k = 0; k < 9; ++k) below[k] = lo[k];
-      for (;;) {
-        bool more = false;
+      for (int k = 0; k < 9; ++k) maxlen = max(maxlen, len[k]);
+      const unsigned key0 = lds_address(rec) + 12u;  // LDS address of record 0's key
+      unsigned at[9], end[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        at[k] = key0 + (len[k] > 0 ? 16u * (unsigned)lo[k] : 16u) - 16u;
+        end[k] = at[k] + 16u * (unsigned)len[k];
+      }
+      for (unsigned step = maxlen > 0 ? 16u << (31 - __clz(maxlen)) : 0u; step >= 16u; step >>= 1) {
+        unsigned pr[9];
+        int kv[9];
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-          if (len[k] > 0) {
-            more = true;
-            const int half = len[k] >> 1;
-            if (rec_key(rec, below[k] + half) < hp) {
-              below[k] += half + 1;
-              len[k] -= half + 1;
-            } else {
-              len[k] = half;
-            }
-          }
+          if (k == 4) continue;  // the hit's own tile
+          pr[k] = min(at[k] + step, end[k]);
+          kv[k] = lds_load_int(pr[k]);
         }
-        if (!more) break;
-      }
 #pragma unroll
-      for (int k = 0; k < 9; ++k) below[k] -= lo[k];
+        for (int k = 0; k < 9; ++k)
+          if (k != 4) at[k] = kv[k] < hp ? pr[k] : at[k];
+      }
+      int below[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) below[k] = (int)(at[k] - (end[k] - 16u * (unsigned)len[k])) >> 4;
 #pragma unroll
       for (int dy = 0; dy < 2; ++dy)
 #pragma unroll
