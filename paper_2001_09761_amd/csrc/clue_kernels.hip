@@ -585,7 +585,8 @@ struct Region {
 
 // Region metadata in LDS (pointers into the workgroup's shared memory; ts and
 // qoff live in the dynamic part, sized for the configured block and halo):
-//   ts[r*(rw+1) + c]  LDS offset of region tile (r, c); c = rw is the row end
+//   ts[r*(rw+1) + c]  LDS offset of region tile (r, c); c = rw is the row end,
+//                     and ts[rh*(rw+1)] repeats the last row's end
 //   row_gs[r]         global slot of the first hit of region row r
 //   row_lo[r]         LDS offset of region row r (row_lo[rh] = total)
 //   core_lo[r]        prefix of core-hit counts over core rows
@@ -669,6 +670,9 @@ __device__ __forceinline__ void region_setup(const Geom& g, const Arena& a, Regi
     const int r = k / per_row;
     L.ts[k] = L.row_lo[r] + (L.ts[k] - L.row_gs[r]);
   }
+  // one entry past the last row's end, equal to it: (ntile - 1, ntile) is an
+  // empty tile that searches may read in place of a tile they do not need
+  if (threadIdx.x == 0) L.ts[ntile] = L.row_lo[R.rh];
   __syncthreads();
   R.total = L.row_lo[R.rh];
 }
@@ -1158,14 +1162,21 @@ __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, co
           const int ax = tc - dx, ay = tr - dy;
           qv[dy][dx] = ax >= qx0 && ax <= qx1 && ay >= qy0 && ay <= qy1;
         }
-      // lower bounds in the needed neighbour tiles, the (up to eight) binary
-      // searches advanced in lockstep so their LDS loads overlap
+      // lower bounds in the needed neighbour tiles. The tile offsets are read
+      // without a branch: a neighbour that is not needed (or lies outside the
+      // region) reads the empty pair after the last row's end.
+      const int rm = max(tr - 1, 0) * per_row, r0 = tl - tc, rp = min(tr + 1, R.rh - 1) * per_row;
+      const int cm = max(tc - 1, 0), cp = min(tc + 1, R.rw - 1);
+      const int empty = R.rh * per_row - 1;
       int lo[9], len[9];
 #pragma unroll
       for (int oy = -1; oy <= 1; ++oy)
 #pragma unroll
         for (int ox = -1; ox <= 1; ++ox) {
           const int k = (oy + 1) * 3 + ox + 1;
+          lo[k] = 0;
+          len[k] = 0;
+          if (k == 4) continue;  // the hit's own tile
           bool need = false;
 #pragma unroll
           for (int dy = 0; dy < 2; ++dy)
@@ -1173,14 +1184,10 @@ __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, co
             for (int dx = 0; dx < 2; ++dx)
               need |= qv[dy][dx] && (ox == -dx || ox == 1 - dx) && (oy == -dy || oy == 1 - dy);
           const int nx = tc + ox, ny = tr + oy;
-          need &= (ox != 0 || oy != 0) && nx >= 0 && nx < R.rw && ny >= 0 && ny < R.rh;
-          lo[k] = 0;
-          len[k] = 0;
-          if (need) {
-            const int nt = ny * per_row + nx;
-            lo[k] = L.ts[nt];
-            len[k] = L.ts[nt + 1] - lo[k];
-          }
+          need &= nx >= 0 && nx < R.rw && ny >= 0 && ny < R.rh;
+          const int nt = need ? (oy < 0 ? rm : oy > 0 ? rp : r0) + (ox < 0 ? cm : ox > 0 ? cp : tc) : empty;
+          lo[k] = L.ts[nt];
+          len[k] = L.ts[nt + 1] - lo[k];
         }
       // The searches share one power-of-two step sequence, from the largest
       // of the tiles down to one record. Each holds the LDS address of its
@@ -1197,37 +1204,53 @@ __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, co
       unsigned at[9], end[9];
 #pragma unroll
       for (int k = 0; k < 9; ++k) {
-        at[k] = key0 + (len[k] > 0 ? 16u * (unsigned)lo[k] : 16u) - 16u;
+        at[k] = len[k] > 0 ? key0 - 16u + 16u * (unsigned)lo[k] : key0;
         end[k] = at[k] + 16u * (unsigned)len[k];
       }
-      for (unsigned step = maxlen > 0 ? 16u << (31 - __clz(maxlen)) : 0u; step >= 16u; step >>= 1) {
+      // per quad, the sum of its three searches' starting addresses
+      unsigned start3[2][2];
+#pragma unroll
+      for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 2; ++dx) {
+          start3[dy][dx] = 0u;
+#pragma unroll
+          for (int oy = -dy; oy <= 1 - dy; ++oy)
+#pragma unroll
+            for (int ox = -dx; ox <= 1 - dx; ++ox)
+              if (ox != 0 || oy != 0) start3[dy][dx] += at[(oy + 1) * 3 + ox + 1];
+        }
+      // at least one step (16 bytes): with every tile empty it changes nothing
+      unsigned step = 16u << max(31 - __clz(maxlen), 0);
+      do {
         unsigned pr[9];
         int kv[9];
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-          if (k == 4) continue;  // the hit's own tile
+          if (k == 4) continue;
           pr[k] = min(at[k] + step, end[k]);
           kv[k] = lds_load_int(pr[k]);
         }
 #pragma unroll
         for (int k = 0; k < 9; ++k)
           if (k != 4) at[k] = kv[k] < hp ? pr[k] : at[k];
-      }
-      int below[9];
-#pragma unroll
-      for (int k = 0; k < 9; ++k) below[k] = (int)(at[k] - (end[k] - 16u * (unsigned)len[k])) >> 4;
+        step >>= 1;
+      } while (step >= 16u);
+      // each quad: the own rank plus the three neighbour counts (16 bytes of
+      // key address per counted key)
 #pragma unroll
       for (int dy = 0; dy < 2; ++dy)
 #pragma unroll
         for (int dx = 0; dx < 2; ++dx) {
           if (!qv[dy][dx]) continue;
-          int pos = own;
+          unsigned below16 = 0u - start3[dy][dx];
 #pragma unroll
           for (int oy = -dy; oy <= 1 - dy; ++oy)
 #pragma unroll
             for (int ox = -dx; ox <= 1 - dx; ++ox)
-              if (ox != 0 || oy != 0) pos += below[(oy + 1) * 3 + ox + 1];
-          qidx[L.qoff[(tr - dy - qy0) * qw + (tc - dx - qx0)] + pos] = (unsigned short)(p * (int)sizeof(float4));
+              if (ox != 0 || oy != 0) below16 += at[(oy + 1) * 3 + ox + 1];
+          qidx[L.qoff[(tr - dy - qy0) * qw + (tc - dx - qx0)] + own + (int)(below16 >> 4)] =
+              (unsigned short)(p * (int)sizeof(float4));
         }
     }
     __syncthreads();
