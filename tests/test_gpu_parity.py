@@ -372,3 +372,32 @@ def test_dense_core_takes_the_global_merge_and_scales():
     print(f"dense core device ms: {times}", flush=True)
     assert times[8000] < 6.0 * times[4000], times
     assert times[8000] < 50.0, times
+
+
+@pytest.mark.parametrize("tuning", [dict(lds_cap=2048, plain_lds_cap=2048, block_x=16, block_y=16),
+                                    dict(lds_cap=1280, plain_lds_cap=1280)])
+@pytest.mark.parametrize("batched", [False, True])
+def test_staged_dense_tiles_long_lower_bound_searches(tuning, batched):
+    """Tiles of 600, 250, 128 (a power of two) and 1 hits side by side, plus
+    sparse hits, all in one staged region (an LDS cap above the region's
+    total): the quad-list build's lower-bound searches then take ten
+    power-of-two steps, with probes clamped at the ends of tiles of every
+    size, including empty ones. Every output equals the oracle's."""
+    rng = np.random.default_rng(21)
+
+    def box(n, x0, x1, y0, y1):
+        return rng.uniform(x0, x1, n).astype(np.float32), rng.uniform(y0, y1, n).astype(np.float32)
+
+    parts = [box(600, 4.1, 7.9, 4.1, 7.9), box(250, 8.2, 11.9, 4.1, 7.9), box(128, 4.1, 7.9, 8.2, 11.9),
+             (np.array([10.0], np.float32), np.array([10.0], np.float32)), box(100, 0.0, 20.0, 0.0, 20.0)]
+    x = np.concatenate([p[0] for p in parts])
+    y = np.concatenate([p[1] for p in parts])
+    layer = np.zeros(x.size, np.int32)
+    xs, ys = box(300, 0.0, 20.0, 0.0, 20.0)  # a sparse second layer
+    x, y = np.concatenate([x, xs]), np.concatenate([y, ys])
+    layer = np.concatenate([layer, np.ones(300, np.int32)])
+    order = rng.permutation(x.size)  # caller order unrelated to position
+    ev = dict(x=x[order], y=y[order], layer=layer[order], energy=rng.uniform(0.1, 1.0, x.size).astype(np.float32))
+    p = dict(ADV_P, n_layers=2)
+    print(f"staged dense tiles: {x.size} hits, tuning {tuning}, batched {batched}", flush=True)
+    assert_parity(gpu_run(ev, p, batched=batched, tuning=tuning), _ref(ev, p), where="staged dense tiles")
