@@ -770,7 +770,7 @@ __device__ __forceinline__ Window query_window(const Geom& g, float w, float xi,
 // in ascending j. Tiles list their hits in ascending index; a query first marks
 // the passing hits of each window tile in a 64-bit mask, then merges only the
 // passing hits of the (at most MAXL x MAXL) sorted tile lists.
-// Records: (x, y, E, hit index as bits).
+// Staged records: (x, y, E), with the hit indices in an array beside them.
 // ---------------------------------------------------------------------------
 // exp(x) for x <= 0 as one fixed binary32 evaluation, after Cody and Waite's
 // range reduction: x = k ln2 + r with k = floor(x / ln2 + 1/2) and ln2 split
@@ -832,15 +832,22 @@ __device__ __forceinline__ float kernel_term(float d2, float ka, float e) {
   }
 }
 
+// A staged density record: 12 bytes, so that the records that one wave reads
+// at once spread over more LDS banks than 16-byte records would; the hit
+// indices (the sort keys) sit in an array of their own.
+struct Rec3 {
+  float x, y, e;
+};
+
 template <int MAXL, int K>
-__device__ __forceinline__ float density_merge_full(const float4* __restrict__ rec, const int* lo, const int* hi, float xi, float yi,
-                                    float dc2, float ka) {
+__device__ __forceinline__ float density_merge_full(const Rec3* __restrict__ rec, const int* __restrict__ keys, const int* lo,
+                                                   const int* hi, float xi, float yi, float dc2, float ka) {
   constexpr int NL = MAXL * MAXL;
   int cur[NL], head[NL];
 #pragma unroll
   for (int k = 0; k < NL; ++k) {
     cur[k] = lo[k];
-    head[k] = cur[k] < hi[k] ? __float_as_int(rec[cur[k]].w) : INT_MAX;
+    head[k] = cur[k] < hi[k] ? keys[cur[k]] : INT_MAX;
   }
   float acc = 0.0f;
   for (;;) {
@@ -852,16 +859,16 @@ __device__ __forceinline__ float density_merge_full(const float4* __restrict__ r
 #pragma unroll
     for (int k = 0; k < NL; ++k)
       if (head[k] == m) p = cur[k];
-    const float4 r = rec[p];
+    const Rec3 r = rec[p];
     const float d2 = dist2(xi, yi, r.x, r.y);
-    if (d2 < dc2) acc = __fadd_rn(acc, kernel_term<K>(d2, ka, r.z));
+    if (d2 < dc2) acc = __fadd_rn(acc, kernel_term<K>(d2, ka, r.e));
     const int np = p + 1;
     int nh = INT_MAX;
     bool more = false;
 #pragma unroll
     for (int k = 0; k < NL; ++k)
       if (head[k] == m) more = np < hi[k];
-    if (more) nh = __float_as_int(rec[np].w);
+    if (more) nh = keys[np];
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
       if (head[k] == m) {
@@ -879,8 +886,8 @@ __device__ __forceinline__ int lowbit64(unsigned lo, unsigned hi) {
 }
 
 template <int MAXL, int K>
-__device__ __forceinline__ float density_two_pass(const float4* __restrict__ rec, const int* lo, const int* hi,
-                                                  float xi, float yi, float dc2, float ka) {
+__device__ __forceinline__ float density_two_pass(const Rec3* __restrict__ rec, const int* __restrict__ keys, const int* lo,
+                                                  const int* hi, float xi, float yi, float dc2, float ka) {
   constexpr int NL = MAXL * MAXL;
   unsigned mlo[NL], mhi[NL];
   bool big = false;
@@ -890,7 +897,7 @@ __device__ __forceinline__ float density_two_pass(const float4* __restrict__ rec
     mhi[k] = 0u;
     const int len = hi[k] - lo[k];
     big |= len > 64;
-    const float4* base = rec + lo[k];
+    const Rec3* base = rec + lo[k];
     const int n0 = min(len, 32);
     int c = 0;
     for (; c + 3 < n0; c += 4) {
@@ -913,7 +920,7 @@ __device__ __forceinline__ float density_two_pass(const float4* __restrict__ rec
       mhi[k] |= (dist2(xi, yi, q.x, q.y) < dc2 ? 1u : 0u) << (c - 32);
     }
   }
-  if (big) return density_merge_full<MAXL, K>(rec, lo, hi, xi, yi, dc2, ka);
+  if (big) return density_merge_full<MAXL, K>(rec, keys, lo, hi, xi, yi, dc2, ka);
   // heads of the lists; with the flat kernel the head's energy is kept,
   // otherwise the selected head is re-read from LDS when it is added
   int hh[NL];
@@ -923,9 +930,9 @@ __device__ __forceinline__ float density_two_pass(const float4* __restrict__ rec
     hh[k] = INT_MAX;
     if constexpr (K == 0) ee[k] = 0.0f;
     if (mlo[k] | mhi[k]) {
-      const float4 r = rec[lo[k] + lowbit64(mlo[k], mhi[k])];
-      hh[k] = __float_as_int(r.w);
-      if constexpr (K == 0) ee[k] = r.z;
+      const int j = lo[k] + lowbit64(mlo[k], mhi[k]);
+      hh[k] = keys[j];
+      if constexpr (K == 0) ee[k] = rec[j].e;
     }
   }
   float acc = 0.0f;
@@ -951,23 +958,28 @@ __device__ __forceinline__ float density_two_pass(const float4* __restrict__ rec
     if constexpr (K == 0) {
       acc = __fadd_rn(acc, e);
     } else {
-      const float4 rs = rec[base + lowbit64(ml, mh)];
-      acc = __fadd_rn(acc, kernel_term<K>(dist2(xi, yi, rs.x, rs.y), ka, rs.z));
+      const Rec3 rs = rec[base + lowbit64(ml, mh)];
+      acc = __fadd_rn(acc, kernel_term<K>(dist2(xi, yi, rs.x, rs.y), ka, rs.e));
     }
     if (ml)
       ml &= ml - 1u;
     else
       mh &= mh - 1u;
     const bool more = (ml | mh) != 0u;
-    float4 r = make_float4(0.0f, 0.0f, 0.0f, __int_as_float(INT_MAX));
-    if (more) r = rec[base + lowbit64(ml, mh)];
+    int nk = INT_MAX;
+    float ne = 0.0f;
+    if (more) {
+      const int j = base + lowbit64(ml, mh);
+      nk = keys[j];
+      ne = rec[j].e;
+    }
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
       if (hh[k] == m) {
         mlo[k] = ml;
         mhi[k] = mh;
-        hh[k] = __float_as_int(r.w);
-        if constexpr (K == 0) ee[k] = r.z;
+        hh[k] = nk;
+        if constexpr (K == 0) ee[k] = ne;
       }
     }
   }
@@ -1017,14 +1029,18 @@ __device__ __forceinline__ float density_global(const Geom& g, const Arena& a, i
 }
 
 // Hit index of an LDS record.
-__device__ __forceinline__ int rec_key(const float4* rec, int j) { return __float_as_int(rec[j].w); }
 
-// Quad-list entries are byte offsets of records (a staged position times 16,
+
+// Quad-list entries are byte offsets of records (a staged position times 12,
 // below 2^15 for every LDS cap), so a scan adds no index scaling.
-__device__ __forceinline__ float4 rec_at(const float4* rec, int byte_off) {
-  return *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(rec) + byte_off);
+// One 12-byte LDS load (a three-float vector at 4-byte alignment).
+typedef float Float3 __attribute__((ext_vector_type(3)));
+typedef Float3 Float3A4 __attribute__((aligned(4)));
+__device__ __forceinline__ Rec3 rec_at(const Rec3* rec, int byte_off) {
+  const Float3 v = *reinterpret_cast<const Float3A4*>(reinterpret_cast<const char*>(rec) + byte_off);
+  return Rec3{v.x, v.y, v.z};
 }
-static_assert(kMaxLdsCap * 16 <= 65536, "quad-list byte offsets are 16-bit");
+static_assert(kMaxLdsCap * sizeof(Rec3) <= 65536, "quad-list byte offsets are 16-bit");
 // Byte address of a shared-memory object in the workgroup's LDS, and a load
 // from such an address: loops that step through LDS by byte address then need
 // no base register added per access.
@@ -1036,16 +1052,16 @@ __device__ __forceinline__ int lds_load_int(unsigned addr) {
 }
 static_assert(kMaxRegionRows <= 64 && kMaxRegionTiles <= 1024, "a staged tile id is (row << 10) | column in 16 bits");
 
-// Density over a staged region (records x, y, E, index; each tile in
-// ascending hit index). With MAXL == 2 every query window lies inside the
+// Density over a staged region (records x, y, E and their hit indices; each
+// tile in ascending hit index). With MAXL == 2 every query window lies inside the
 // 2x2 tile quad anchored at its lower-left window tile; the quads a core
 // query can use are merged once per region into index-ordered lists (byte
 // offsets of the records), so each query is one linear scan in ascending
 // hit index. Otherwise (or if the quads do not fit) a query merges its
 // window's tile lists itself.
 template <int MAXL, int K>
-__device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, const Region& R, RegionLds& L, float4* rec,
-                                               unsigned short* stile, unsigned short* qidx, bool keep) {
+__device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, const Region& R, RegionLds& L, Rec3* rec,
+                                               int* keys, unsigned short* stile, unsigned short* qidx, bool keep) {
   const int per_row = R.rw + 1;
   const int64_t ubase = (int64_t)R.unit * g.tpl;
   const int ntl = R.rh * per_row;
@@ -1063,19 +1079,24 @@ __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, co
   // copy the records (tiles are already in ascending hit index); every
   // global load of a lane is issued before its first LDS store
   for (int base = 0; base < R.total; base += kStagePer * kWG) {
-    float4 v[kStagePer];
+    Rec3 v[kStagePer];
+    int h[kStagePer];
 #pragma unroll
     for (int k = 0; k < kStagePer; ++k) {
       const int p = base + (int)threadIdx.x + k * kWG;
       if (p < R.total) {
         const int sl = slot_of(L, stile[p] >> 10, p);
-        v[k] = make_float4(a.xs[sl], a.ys[sl], a.es[sl], __int_as_float(a.hs[sl]));
+        v[k] = Rec3{a.xs[sl], a.ys[sl], a.es[sl]};
+        h[k] = a.hs[sl];
       }
     }
 #pragma unroll
     for (int k = 0; k < kStagePer; ++k) {
       const int p = base + (int)threadIdx.x + k * kWG;
-      if (p < R.total) rec[p] = v[k];
+      if (p < R.total) {
+        rec[p] = v[k];
+        keys[p] = h[k];
+      }
     }
   }
   // quads anchored at region tiles [qx0, qx1] x [qy0, qy1]
@@ -1121,7 +1142,7 @@ __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, co
         const int t = ty * per_row + tx;
         cur[k] = dup ? 0 : L.ts[t];
         end[k] = dup ? 0 : L.ts[t + 1];
-        key[k] = cur[k] < end[k] ? rec_key(rec, cur[k]) : INT_MAX;
+        key[k] = cur[k] < end[k] ? keys[cur[k]] : INT_MAX;
       }
       const int out = L.qoff[q], n = L.qoff[q + 1] - out;
       for (int i = 0; i < n; ++i) {
@@ -1129,9 +1150,9 @@ __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, co
         const bool s0 = key[0] == m, s1 = !s0 && key[1] == m, s2 = !s0 && !s1 && key[2] == m;
         const int pk = s0 ? cur[0] : (s1 ? cur[1] : (s2 ? cur[2] : cur[3]));
         const int ek = s0 ? end[0] : (s1 ? end[1] : (s2 ? end[2] : end[3]));
-        qidx[out + i] = (unsigned short)(pk * (int)sizeof(float4));
+        qidx[out + i] = (unsigned short)(pk * (int)sizeof(Rec3));
         const int np = pk + 1;
-        const int nk = np < ek ? rec_key(rec, np) : INT_MAX;
+        const int nk = np < ek ? keys[np] : INT_MAX;
         const bool s3 = !s0 && !s1 && !s2;
         cur[0] = s0 ? np : cur[0];
         key[0] = s0 ? nk : key[0];
@@ -1152,7 +1173,7 @@ __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, co
     for (int p = threadIdx.x; p < R.total; p += kWG) {
       const int tr = stile[p] >> 10, tc = stile[p] & 1023;
       const int tl = tr * per_row + tc;
-      const int hp = rec_key(rec, p);
+      const int hp = keys[p];
       const int own = p - L.ts[tl];
       bool qv[2][2];
 #pragma unroll
@@ -1200,12 +1221,12 @@ __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, co
       int maxlen = 0;
 #pragma unroll
       for (int k = 0; k < 9; ++k) maxlen = max(maxlen, len[k]);
-      const unsigned key0 = lds_address(rec) + 12u;  // LDS address of record 0's key
+      const unsigned key0 = lds_address(keys);  // LDS address of record 0's key
       unsigned at[9], end[9];
 #pragma unroll
       for (int k = 0; k < 9; ++k) {
-        at[k] = len[k] > 0 ? key0 - 16u + 16u * (unsigned)lo[k] : key0;
-        end[k] = at[k] + 16u * (unsigned)len[k];
+        at[k] = len[k] > 0 ? key0 - 4u + 4u * (unsigned)lo[k] : key0;
+        end[k] = at[k] + 4u * (unsigned)len[k];
       }
       // per quad, the sum of its three searches' starting addresses
       unsigned start3[2][2];
@@ -1220,8 +1241,8 @@ __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, co
             for (int ox = -dx; ox <= 1 - dx; ++ox)
               if (ox != 0 || oy != 0) start3[dy][dx] += at[(oy + 1) * 3 + ox + 1];
         }
-      // at least one step (16 bytes): with every tile empty it changes nothing
-      unsigned step = 16u << max(31 - __clz(maxlen), 0);
+      // at least one step (4 bytes): with every tile empty it changes nothing
+      unsigned step = 4u << max(31 - __clz(maxlen), 0);
       do {
         unsigned pr[9];
         int kv[9];
@@ -1235,22 +1256,22 @@ __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, co
         for (int k = 0; k < 9; ++k)
           if (k != 4) at[k] = kv[k] < hp ? pr[k] : at[k];
         step >>= 1;
-      } while (step >= 16u);
-      // each quad: the own rank plus the three neighbour counts (16 bytes of
+      } while (step >= 4u);
+      // each quad: the own rank plus the three neighbour counts (4 bytes of
       // key address per counted key)
 #pragma unroll
       for (int dy = 0; dy < 2; ++dy)
 #pragma unroll
         for (int dx = 0; dx < 2; ++dx) {
           if (!qv[dy][dx]) continue;
-          unsigned below16 = 0u - start3[dy][dx];
+          unsigned below4 = 0u - start3[dy][dx];
 #pragma unroll
           for (int oy = -dy; oy <= 1 - dy; ++oy)
 #pragma unroll
             for (int ox = -dx; ox <= 1 - dx; ++ox)
-              if (ox != 0 || oy != 0) below16 += at[(oy + 1) * 3 + ox + 1];
-          qidx[L.qoff[(tr - dy - qy0) * qw + (tc - dx - qx0)] + own + (int)(below16 >> 4)] =
-              (unsigned short)(p * (int)sizeof(float4));
+              if (ox != 0 || oy != 0) below4 += at[(oy + 1) * 3 + ox + 1];
+          qidx[L.qoff[(tr - dy - qy0) * qw + (tc - dx - qx0)] + own + (int)(below4 >> 2)] =
+              (unsigned short)(p * (int)sizeof(Rec3));
         }
     }
     __syncthreads();
@@ -1263,7 +1284,7 @@ __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, co
     int row, p;
     core_query(L, R, q, cr, row, p);
     const int slot = slot_of(L, row, p);
-    const float4 me = rec[p];
+    const Rec3 me = rec[p];
     const float xi = me.x, yi = me.y;
     const Window W = query_window(g, g.win_dc, xi, yi);
     const int tx0 = W.x0 - R.rx0, tx1 = W.x1 - R.rx0, ty0 = W.y0 - R.ry0, ty1 = W.y1 - R.ry0;
@@ -1277,22 +1298,22 @@ __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, co
       // loads batched four at a time; additions stay in ascending index order
       for (; qp < qe4; qp += 4) {
         const int i0 = qp[0], i1 = qp[1], i2 = qp[2], i3 = qp[3];
-        const float4 r0 = rec_at(rec, i0), r1 = rec_at(rec, i1), r2 = rec_at(rec, i2), r3 = rec_at(rec, i3);
+        const Rec3 r0 = rec_at(rec, i0), r1 = rec_at(rec, i1), r2 = rec_at(rec, i2), r3 = rec_at(rec, i3);
         const float d0 = dist2(xi, yi, r0.x, r0.y), d1 = dist2(xi, yi, r1.x, r1.y);
         const float d2 = dist2(xi, yi, r2.x, r2.y), d3 = dist2(xi, yi, r3.x, r3.y);
-        const float a0 = __fadd_rn(rho, kernel_term<K>(d0, g.ka, r0.z));
+        const float a0 = __fadd_rn(rho, kernel_term<K>(d0, g.ka, r0.e));
         rho = d0 < g.dc2 ? a0 : rho;
-        const float a1 = __fadd_rn(rho, kernel_term<K>(d1, g.ka, r1.z));
+        const float a1 = __fadd_rn(rho, kernel_term<K>(d1, g.ka, r1.e));
         rho = d1 < g.dc2 ? a1 : rho;
-        const float a2 = __fadd_rn(rho, kernel_term<K>(d2, g.ka, r2.z));
+        const float a2 = __fadd_rn(rho, kernel_term<K>(d2, g.ka, r2.e));
         rho = d2 < g.dc2 ? a2 : rho;
-        const float a3 = __fadd_rn(rho, kernel_term<K>(d3, g.ka, r3.z));
+        const float a3 = __fadd_rn(rho, kernel_term<K>(d3, g.ka, r3.e));
         rho = d3 < g.dc2 ? a3 : rho;
       }
       for (; qp < qe; ++qp) {
-        const float4 r = rec_at(rec, *qp);
+        const Rec3 r = rec_at(rec, *qp);
         const float d = dist2(xi, yi, r.x, r.y);
-        const float a = __fadd_rn(rho, kernel_term<K>(d, g.ka, r.z));
+        const float a = __fadd_rn(rho, kernel_term<K>(d, g.ka, r.e));
         rho = d < g.dc2 ? a : rho;
       }
     } else if (ok) {
@@ -1311,13 +1332,13 @@ __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, co
             hi[k] = 0;
           }
         }
-      rho = density_two_pass<MAXL, K>(rec, lo, hi, xi, yi, g.dc2, g.ka);
+      rho = density_two_pass<MAXL, K>(rec, keys, lo, hi, xi, yi, g.dc2, g.ka);
     } else {
       atomicOr(a.err, (uint32_t)E_WINDOW);
       rho = density_global<K>(g, a, ubase, xi, yi);
     }
     a.rho[slot] = rho;
-    if (keep) a.rho_out[__float_as_int(me.w)] = rho;
+    if (keep) a.rho_out[keys[p]] = rho;
   }
 }
 
@@ -1371,8 +1392,9 @@ __global__ __launch_bounds__(kWG, density_min_waves(MAXL, K)) void k_density(Des
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int s_rows[kRowMetaInts];
   __shared__ int s_item;
-  float4* rec = reinterpret_cast<float4*>(smem);
-  unsigned short* stile = reinterpret_cast<unsigned short*>(rec + g.lds_cap);
+  Rec3* rec = reinterpret_cast<Rec3*>(smem);
+  int* keys = reinterpret_cast<int*>(rec + g.lds_cap);
+  unsigned short* stile = reinterpret_cast<unsigned short*>(keys + g.lds_cap);
   unsigned short* qidx = stile + g.lds_cap;
   int* meta = reinterpret_cast<int*>(smem + lds_records_density(g.lds_cap));
   RegionLds L = region_lds(s_rows, meta, meta + g.ts_ints);
@@ -1387,7 +1409,7 @@ __global__ __launch_bounds__(kWG, density_min_waves(MAXL, K)) void k_density(Des
     region_setup(g, a, R, L);
     if (L.core_lo[R.ch] == 0) continue;
     if (R.total <= g.lds_cap) {
-      density_staged<MAXL, K>(g, a, R, L, rec, stile, qidx, keep);
+      density_staged<MAXL, K>(g, a, R, L, rec, keys, stile, qidx, keep);
       continue;
     }
     // too dense: the four quarter blocks, then single tiles
@@ -1399,7 +1421,7 @@ __global__ __launch_bounds__(kWG, density_min_waves(MAXL, K)) void k_density(Des
         region_setup(g, a, R, L);
         if (L.core_lo[R.ch] == 0) continue;
         if (R.total <= g.lds_cap) {
-          density_staged<MAXL, K>(g, a, R, L, rec, stile, qidx, keep);
+          density_staged<MAXL, K>(g, a, R, L, rec, keys, stile, qidx, keep);
           continue;
         }
         for (int ty = sy; ty <= ey; ++ty)
@@ -1408,7 +1430,7 @@ __global__ __launch_bounds__(kWG, density_min_waves(MAXL, K)) void k_density(Des
             region_setup(g, a, R, L);
             if (L.core_lo[R.ch] == 0) continue;
             if (R.total <= g.lds_cap)
-              density_staged<MAXL, K>(g, a, R, L, rec, stile, qidx, keep);
+              density_staged<MAXL, K>(g, a, R, L, rec, keys, stile, qidx, keep);
             else
               spill_region(g, a, R, C_SPILL_RHO, kWG);
           }
@@ -2117,9 +2139,9 @@ __global__ void k_set_desc(RunDesc d, RunDesc* dd) {
 // ---------------------------------------------------------------------------
 // Host launches.
 // ---------------------------------------------------------------------------
-// Dynamic LDS of the density kernel: per staged hit a float4 record, a 16-bit
-// tile id and four 16-bit quad-list entries, then the region's tile offsets
-// and quad-list offsets.
+// Dynamic LDS of the density kernel: per staged hit a 12-byte record, its hit
+// index, a 16-bit tile id and four 16-bit quad-list entries, then the region's
+// tile offsets and quad-list offsets.
 int lds_bytes_for(const Geom& g) { return lds_records_density(g.lds_cap) + 4 * (g.ts_ints + g.q_ints); }
 // Nearest-higher: per staged hit a float4 record, a 16-bit queue entry and its
 // region row (a byte), then the region's tile offsets.
