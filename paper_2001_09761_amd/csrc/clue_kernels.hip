@@ -1028,12 +1028,11 @@ __device__ __forceinline__ float density_global(const Geom& g, const Arena& a, i
   return acc;
 }
 
-// Hit index of an LDS record.
-
-
 // Quad-list entries are byte offsets of records (a staged position times 12,
 // below 2^15 for every LDS cap), so a scan adds no index scaling.
-// One 12-byte LDS load (a three-float vector at 4-byte alignment).
+// The record is read as one three-float vector; at the density kernel's
+// occupancy bound the compiler issues it as a two-word and a one-word LDS
+// load from the same address.
 typedef float Float3 __attribute__((ext_vector_type(3)));
 typedef Float3 Float3A4 __attribute__((aligned(4)));
 __device__ __forceinline__ Rec3 rec_at(const Rec3* rec, int byte_off) {
