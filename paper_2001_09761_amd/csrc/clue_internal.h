@@ -17,7 +17,7 @@ constexpr int kMaxRegionTiles = 640;   // staged region tiles, rows x (cols + 1)
 constexpr int kMaxRegionRows = 64;
 constexpr int kDefaultLdsCap = 960;    // staged hits per workgroup (fast path)
 constexpr int kMaxLdsCap = 2048;
-// Bytes of the density kernel's per-hit LDS arrays (12-byte record, 32-bit
+// Bytes of the density kernel's per-hit LDS arrays (16 bytes of record and
 // hit index, 16-bit tile id, four 16-bit quad entries), rounded up to 16.
 __host__ __device__ constexpr int lds_records_density(int lds_cap) { return (lds_cap * (12 + 4 + 2 + 8) + 15) & ~15; }
 // ... and of the nearest-higher kernel's (float4 record, 16-bit queue entry,

@@ -832,22 +832,84 @@ __device__ __forceinline__ float kernel_term(float d2, float ka, float e) {
   }
 }
 
-// A staged density record: 12 bytes, so that the records that one wave reads
-// at once spread over more LDS banks than 16-byte records would; the hit
-// indices (the sort keys) sit in an array of their own.
+// A staged record's position and energy.
 struct Rec3 {
   float x, y, e;
 };
 
-template <int MAXL, int K>
-__device__ __forceinline__ float density_merge_full(const Rec3* __restrict__ rec, const int* __restrict__ keys, const int* lo,
+// Staged density records, 16 bytes per hit in both layouts:
+// * the two-tile instance keeps 12-byte records (x, y, E) with the hit
+//   indices (the sort keys) in an array of their own, so that the records one
+//   wave reads at once, and the keys the quad-list build probes, spread over
+//   more LDS banks than 16-byte records would;
+// * the three-tile instance keeps 16-byte records (x, y, E, hit index), whose
+//   mask loop reads the (x, y) of two records in one 64-bit pair load.
+template <int MAXL>
+struct Staged {
+  static constexpr bool kSplit = MAXL == 2;
+  static constexpr int kRecBytes = kSplit ? 12 : 16;
+  static constexpr int kKeyShift = kSplit ? 2 : 4;  // log2 of the LDS stride between keys
+  unsigned char* base;
+  int cap;
+  __device__ __forceinline__ const float* rec(int j) const {
+    return reinterpret_cast<const float*>(base + kRecBytes * j);
+  }
+  __device__ __forceinline__ float2 xy(int j) const {
+    if constexpr (kSplit) {
+      const float* r = rec(j);
+      return make_float2(r[0], r[1]);
+    } else {
+      return *reinterpret_cast<const float2*>(rec(j));
+    }
+  }
+  __device__ __forceinline__ float e(int j) const { return rec(j)[2]; }
+  __device__ __forceinline__ const int* key_ptr(int j) const {
+    if constexpr (kSplit) return reinterpret_cast<const int*>(base + 12 * cap) + j;
+    else return reinterpret_cast<const int*>(base + 16 * j + 12);
+  }
+  __device__ __forceinline__ int key(int j) const { return *key_ptr(j); }
+  __device__ __forceinline__ void put(int j, float x, float y, float en, int h) const {
+    if constexpr (kSplit) {
+      *reinterpret_cast<Rec3*>(base + 12 * j) = Rec3{x, y, en};
+      *const_cast<int*>(key_ptr(j)) = h;
+    } else {
+      *reinterpret_cast<float4*>(base + 16 * j) = make_float4(x, y, en, __int_as_float(h));
+    }
+  }
+  // The record at a quad-list entry (its byte offset). As one three- or
+  // four-float vector; at the density kernel's occupancy bound the compiler
+  // issues the split layout's as a two-word and a one-word LDS load from the
+  // same address.
+  __device__ __forceinline__ Rec3 at(int byte_off) const {
+    if constexpr (kSplit) {
+      typedef float Float3 __attribute__((ext_vector_type(3)));
+      typedef Float3 Float3A4 __attribute__((aligned(4)));
+      const Float3 v = *reinterpret_cast<const Float3A4*>(base + byte_off);
+      return Rec3{v.x, v.y, v.z};
+    } else {
+      const float4 v = *reinterpret_cast<const float4*>(base + byte_off);
+      return Rec3{v.x, v.y, v.z};
+    }
+  }
+};
+
+// Energy and hit index of a staged record, for both layouts (a 16-byte
+// record carries its index in the fourth word; a 12-byte record's index is in
+// the array beside the records).
+__device__ __forceinline__ float rec_e(const float4& r) { return r.z; }
+__device__ __forceinline__ float rec_e(const Rec3& r) { return r.e; }
+__device__ __forceinline__ int rec_key(const float4* rec, const int*, int j) { return __float_as_int(rec[j].w); }
+__device__ __forceinline__ int rec_key(const Rec3*, const int* keys, int j) { return keys[j]; }
+
+template <int MAXL, int K, typename T>
+__device__ __forceinline__ float density_merge_full(const T* __restrict__ rec, const int* __restrict__ keys, const int* lo,
                                                    const int* hi, float xi, float yi, float dc2, float ka) {
   constexpr int NL = MAXL * MAXL;
   int cur[NL], head[NL];
 #pragma unroll
   for (int k = 0; k < NL; ++k) {
     cur[k] = lo[k];
-    head[k] = cur[k] < hi[k] ? keys[cur[k]] : INT_MAX;
+    head[k] = cur[k] < hi[k] ? rec_key(rec, keys, cur[k]) : INT_MAX;
   }
   float acc = 0.0f;
   for (;;) {
@@ -859,16 +921,16 @@ __device__ __forceinline__ float density_merge_full(const Rec3* __restrict__ rec
 #pragma unroll
     for (int k = 0; k < NL; ++k)
       if (head[k] == m) p = cur[k];
-    const Rec3 r = rec[p];
+    const T r = rec[p];
     const float d2 = dist2(xi, yi, r.x, r.y);
-    if (d2 < dc2) acc = __fadd_rn(acc, kernel_term<K>(d2, ka, r.e));
+    if (d2 < dc2) acc = __fadd_rn(acc, kernel_term<K>(d2, ka, rec_e(r)));
     const int np = p + 1;
     int nh = INT_MAX;
     bool more = false;
 #pragma unroll
     for (int k = 0; k < NL; ++k)
       if (head[k] == m) more = np < hi[k];
-    if (more) nh = keys[np];
+    if (more) nh = rec_key(rec, keys, np);
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
       if (head[k] == m) {
@@ -885,8 +947,8 @@ __device__ __forceinline__ int lowbit64(unsigned lo, unsigned hi) {
   return lo ? __builtin_ctz(lo) : 32 + __builtin_ctz(hi);
 }
 
-template <int MAXL, int K>
-__device__ __forceinline__ float density_two_pass(const Rec3* __restrict__ rec, const int* __restrict__ keys, const int* lo,
+template <int MAXL, int K, typename T>
+__device__ __forceinline__ float density_two_pass(const T* __restrict__ rec, const int* __restrict__ keys, const int* lo,
                                                   const int* hi, float xi, float yi, float dc2, float ka) {
   constexpr int NL = MAXL * MAXL;
   unsigned mlo[NL], mhi[NL];
@@ -897,7 +959,7 @@ __device__ __forceinline__ float density_two_pass(const Rec3* __restrict__ rec, 
     mhi[k] = 0u;
     const int len = hi[k] - lo[k];
     big |= len > 64;
-    const Rec3* base = rec + lo[k];
+    const T* base = rec + lo[k];
     const int n0 = min(len, 32);
     int c = 0;
     for (; c + 3 < n0; c += 4) {
@@ -931,8 +993,8 @@ __device__ __forceinline__ float density_two_pass(const Rec3* __restrict__ rec, 
     if constexpr (K == 0) ee[k] = 0.0f;
     if (mlo[k] | mhi[k]) {
       const int j = lo[k] + lowbit64(mlo[k], mhi[k]);
-      hh[k] = keys[j];
-      if constexpr (K == 0) ee[k] = rec[j].e;
+      hh[k] = rec_key(rec, keys, j);
+      if constexpr (K == 0) ee[k] = rec_e(rec[j]);
     }
   }
   float acc = 0.0f;
@@ -958,8 +1020,8 @@ __device__ __forceinline__ float density_two_pass(const Rec3* __restrict__ rec, 
     if constexpr (K == 0) {
       acc = __fadd_rn(acc, e);
     } else {
-      const Rec3 rs = rec[base + lowbit64(ml, mh)];
-      acc = __fadd_rn(acc, kernel_term<K>(dist2(xi, yi, rs.x, rs.y), ka, rs.e));
+      const T rs = rec[base + lowbit64(ml, mh)];
+      acc = __fadd_rn(acc, kernel_term<K>(dist2(xi, yi, rs.x, rs.y), ka, rec_e(rs)));
     }
     if (ml)
       ml &= ml - 1u;
@@ -970,8 +1032,8 @@ __device__ __forceinline__ float density_two_pass(const Rec3* __restrict__ rec, 
     float ne = 0.0f;
     if (more) {
       const int j = base + lowbit64(ml, mh);
-      nk = keys[j];
-      ne = rec[j].e;
+      nk = rec_key(rec, keys, j);
+      ne = rec_e(rec[j]);
     }
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
@@ -1028,18 +1090,9 @@ __device__ __forceinline__ float density_global(const Geom& g, const Arena& a, i
   return acc;
 }
 
-// Quad-list entries are byte offsets of records (a staged position times 12,
-// below 2^15 for every LDS cap), so a scan adds no index scaling.
-// The record is read as one three-float vector; at the density kernel's
-// occupancy bound the compiler issues it as a two-word and a one-word LDS
-// load from the same address.
-typedef float Float3 __attribute__((ext_vector_type(3)));
-typedef Float3 Float3A4 __attribute__((aligned(4)));
-__device__ __forceinline__ Rec3 rec_at(const Rec3* rec, int byte_off) {
-  const Float3 v = *reinterpret_cast<const Float3A4*>(reinterpret_cast<const char*>(rec) + byte_off);
-  return Rec3{v.x, v.y, v.z};
-}
-static_assert(kMaxLdsCap * sizeof(Rec3) <= 65536, "quad-list byte offsets are 16-bit");
+// Quad-list entries are byte offsets of records (a staged position times the
+// record size, below 2^15 for every LDS cap), so a scan adds no index scaling.
+static_assert(kMaxLdsCap * 16 <= 65536, "quad-list byte offsets are 16-bit");
 // Byte address of a shared-memory object in the workgroup's LDS, and a load
 // from such an address: loops that step through LDS by byte address then need
 // no base register added per access.
@@ -1059,8 +1112,9 @@ static_assert(kMaxRegionRows <= 64 && kMaxRegionTiles <= 1024, "a staged tile id
 // hit index. Otherwise (or if the quads do not fit) a query merges its
 // window's tile lists itself.
 template <int MAXL, int K>
-__device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, const Region& R, RegionLds& L, Rec3* rec,
-                                               int* keys, unsigned short* stile, unsigned short* qidx, bool keep) {
+__device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, const Region& R, RegionLds& L,
+                                               const Staged<MAXL>& S, unsigned short* stile, unsigned short* qidx,
+                                               bool keep) {
   const int per_row = R.rw + 1;
   const int64_t ubase = (int64_t)R.unit * g.tpl;
   const int ntl = R.rh * per_row;
@@ -1092,10 +1146,7 @@ __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, co
 #pragma unroll
     for (int k = 0; k < kStagePer; ++k) {
       const int p = base + (int)threadIdx.x + k * kWG;
-      if (p < R.total) {
-        rec[p] = v[k];
-        keys[p] = h[k];
-      }
+      if (p < R.total) S.put(p, v[k].x, v[k].y, v[k].e, h[k]);
     }
   }
   // quads anchored at region tiles [qx0, qx1] x [qy0, qy1]
@@ -1141,7 +1192,7 @@ __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, co
         const int t = ty * per_row + tx;
         cur[k] = dup ? 0 : L.ts[t];
         end[k] = dup ? 0 : L.ts[t + 1];
-        key[k] = cur[k] < end[k] ? keys[cur[k]] : INT_MAX;
+        key[k] = cur[k] < end[k] ? S.key(cur[k]) : INT_MAX;
       }
       const int out = L.qoff[q], n = L.qoff[q + 1] - out;
       for (int i = 0; i < n; ++i) {
@@ -1149,9 +1200,9 @@ __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, co
         const bool s0 = key[0] == m, s1 = !s0 && key[1] == m, s2 = !s0 && !s1 && key[2] == m;
         const int pk = s0 ? cur[0] : (s1 ? cur[1] : (s2 ? cur[2] : cur[3]));
         const int ek = s0 ? end[0] : (s1 ? end[1] : (s2 ? end[2] : end[3]));
-        qidx[out + i] = (unsigned short)(pk * (int)sizeof(Rec3));
+        qidx[out + i] = (unsigned short)(pk * S.kRecBytes);
         const int np = pk + 1;
-        const int nk = np < ek ? keys[np] : INT_MAX;
+        const int nk = np < ek ? S.key(np) : INT_MAX;
         const bool s3 = !s0 && !s1 && !s2;
         cur[0] = s0 ? np : cur[0];
         key[0] = s0 ? nk : key[0];
@@ -1172,7 +1223,7 @@ __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, co
     for (int p = threadIdx.x; p < R.total; p += kWG) {
       const int tr = stile[p] >> 10, tc = stile[p] & 1023;
       const int tl = tr * per_row + tc;
-      const int hp = keys[p];
+      const int hp = S.key(p);
       const int own = p - L.ts[tl];
       bool qv[2][2];
 #pragma unroll
@@ -1220,12 +1271,13 @@ __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, co
       int maxlen = 0;
 #pragma unroll
       for (int k = 0; k < 9; ++k) maxlen = max(maxlen, len[k]);
-      const unsigned key0 = lds_address(keys);  // LDS address of record 0's key
+      constexpr int ks = Staged<MAXL>::kKeyShift;
+      const unsigned key0 = lds_address(S.key_ptr(0));  // LDS address of record 0's key
       unsigned at[9], end[9];
 #pragma unroll
       for (int k = 0; k < 9; ++k) {
-        at[k] = len[k] > 0 ? key0 - 4u + 4u * (unsigned)lo[k] : key0;
-        end[k] = at[k] + 4u * (unsigned)len[k];
+        at[k] = len[k] > 0 ? key0 + (((unsigned)lo[k] - 1u) << ks) : key0;
+        end[k] = at[k] + ((unsigned)len[k] << ks);
       }
       // per quad, the sum of its three searches' starting addresses
       unsigned start3[2][2];
@@ -1240,8 +1292,8 @@ __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, co
             for (int ox = -dx; ox <= 1 - dx; ++ox)
               if (ox != 0 || oy != 0) start3[dy][dx] += at[(oy + 1) * 3 + ox + 1];
         }
-      // at least one step (4 bytes): with every tile empty it changes nothing
-      unsigned step = 4u << max(31 - __clz(maxlen), 0);
+      // at least one step (one key): with every tile empty it changes nothing
+      unsigned step = (1u << ks) << max(31 - __clz(maxlen), 0);
       do {
         unsigned pr[9];
         int kv[9];
@@ -1255,22 +1307,22 @@ __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, co
         for (int k = 0; k < 9; ++k)
           if (k != 4) at[k] = kv[k] < hp ? pr[k] : at[k];
         step >>= 1;
-      } while (step >= 4u);
-      // each quad: the own rank plus the three neighbour counts (4 bytes of
-      // key address per counted key)
+      } while (step >= (1u << ks));
+      // each quad: the own rank plus the three neighbour counts (one key
+      // stride of address per counted key)
 #pragma unroll
       for (int dy = 0; dy < 2; ++dy)
 #pragma unroll
         for (int dx = 0; dx < 2; ++dx) {
           if (!qv[dy][dx]) continue;
-          unsigned below4 = 0u - start3[dy][dx];
+          unsigned below = 0u - start3[dy][dx];
 #pragma unroll
           for (int oy = -dy; oy <= 1 - dy; ++oy)
 #pragma unroll
             for (int ox = -dx; ox <= 1 - dx; ++ox)
-              if (ox != 0 || oy != 0) below4 += at[(oy + 1) * 3 + ox + 1];
-          qidx[L.qoff[(tr - dy - qy0) * qw + (tc - dx - qx0)] + own + (int)(below4 >> 2)] =
-              (unsigned short)(p * (int)sizeof(Rec3));
+              if (ox != 0 || oy != 0) below += at[(oy + 1) * 3 + ox + 1];
+          qidx[L.qoff[(tr - dy - qy0) * qw + (tc - dx - qx0)] + own + (int)(below >> ks)] =
+              (unsigned short)(p * S.kRecBytes);
         }
     }
     __syncthreads();
@@ -1283,7 +1335,7 @@ __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, co
     int row, p;
     core_query(L, R, q, cr, row, p);
     const int slot = slot_of(L, row, p);
-    const Rec3 me = rec[p];
+    const float2 me = S.xy(p);
     const float xi = me.x, yi = me.y;
     const Window W = query_window(g, g.win_dc, xi, yi);
     const int tx0 = W.x0 - R.rx0, tx1 = W.x1 - R.rx0, ty0 = W.y0 - R.ry0, ty1 = W.y1 - R.ry0;
@@ -1297,7 +1349,7 @@ __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, co
       // loads batched four at a time; additions stay in ascending index order
       for (; qp < qe4; qp += 4) {
         const int i0 = qp[0], i1 = qp[1], i2 = qp[2], i3 = qp[3];
-        const Rec3 r0 = rec_at(rec, i0), r1 = rec_at(rec, i1), r2 = rec_at(rec, i2), r3 = rec_at(rec, i3);
+        const Rec3 r0 = S.at(i0), r1 = S.at(i1), r2 = S.at(i2), r3 = S.at(i3);
         const float d0 = dist2(xi, yi, r0.x, r0.y), d1 = dist2(xi, yi, r1.x, r1.y);
         const float d2 = dist2(xi, yi, r2.x, r2.y), d3 = dist2(xi, yi, r3.x, r3.y);
         const float a0 = __fadd_rn(rho, kernel_term<K>(d0, g.ka, r0.e));
@@ -1310,7 +1362,7 @@ __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, co
         rho = d3 < g.dc2 ? a3 : rho;
       }
       for (; qp < qe; ++qp) {
-        const Rec3 r = rec_at(rec, *qp);
+        const Rec3 r = S.at(*qp);
         const float d = dist2(xi, yi, r.x, r.y);
         const float a = __fadd_rn(rho, kernel_term<K>(d, g.ka, r.e));
         rho = d < g.dc2 ? a : rho;
@@ -1331,13 +1383,16 @@ __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, co
             hi[k] = 0;
           }
         }
-      rho = density_two_pass<MAXL, K>(rec, keys, lo, hi, xi, yi, g.dc2, g.ka);
+      if constexpr (Staged<MAXL>::kSplit)
+        rho = density_two_pass<MAXL, K>(reinterpret_cast<const Rec3*>(S.base), S.key_ptr(0), lo, hi, xi, yi, g.dc2, g.ka);
+      else
+        rho = density_two_pass<MAXL, K>(reinterpret_cast<const float4*>(S.base), nullptr, lo, hi, xi, yi, g.dc2, g.ka);
     } else {
       atomicOr(a.err, (uint32_t)E_WINDOW);
       rho = density_global<K>(g, a, ubase, xi, yi);
     }
     a.rho[slot] = rho;
-    if (keep) a.rho_out[keys[p]] = rho;
+    if (keep) a.rho_out[S.key(p)] = rho;
   }
 }
 
@@ -1391,9 +1446,8 @@ __global__ __launch_bounds__(kWG, density_min_waves(MAXL, K)) void k_density(Des
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int s_rows[kRowMetaInts];
   __shared__ int s_item;
-  Rec3* rec = reinterpret_cast<Rec3*>(smem);
-  int* keys = reinterpret_cast<int*>(rec + g.lds_cap);
-  unsigned short* stile = reinterpret_cast<unsigned short*>(keys + g.lds_cap);
+  const Staged<MAXL> S{smem, g.lds_cap};
+  unsigned short* stile = reinterpret_cast<unsigned short*>(smem + 16 * g.lds_cap);  // both layouts: 16 B per hit
   unsigned short* qidx = stile + g.lds_cap;
   int* meta = reinterpret_cast<int*>(smem + lds_records_density(g.lds_cap));
   RegionLds L = region_lds(s_rows, meta, meta + g.ts_ints);
@@ -1408,7 +1462,7 @@ __global__ __launch_bounds__(kWG, density_min_waves(MAXL, K)) void k_density(Des
     region_setup(g, a, R, L);
     if (L.core_lo[R.ch] == 0) continue;
     if (R.total <= g.lds_cap) {
-      density_staged<MAXL, K>(g, a, R, L, rec, keys, stile, qidx, keep);
+      density_staged<MAXL, K>(g, a, R, L, S, stile, qidx, keep);
       continue;
     }
     // too dense: the four quarter blocks, then single tiles
@@ -1420,7 +1474,7 @@ __global__ __launch_bounds__(kWG, density_min_waves(MAXL, K)) void k_density(Des
         region_setup(g, a, R, L);
         if (L.core_lo[R.ch] == 0) continue;
         if (R.total <= g.lds_cap) {
-          density_staged<MAXL, K>(g, a, R, L, rec, keys, stile, qidx, keep);
+          density_staged<MAXL, K>(g, a, R, L, S, stile, qidx, keep);
           continue;
         }
         for (int ty = sy; ty <= ey; ++ty)
@@ -1429,7 +1483,7 @@ __global__ __launch_bounds__(kWG, density_min_waves(MAXL, K)) void k_density(Des
             region_setup(g, a, R, L);
             if (L.core_lo[R.ch] == 0) continue;
             if (R.total <= g.lds_cap)
-              density_staged<MAXL, K>(g, a, R, L, rec, keys, stile, qidx, keep);
+              density_staged<MAXL, K>(g, a, R, L, S, stile, qidx, keep);
             else
               spill_region(g, a, R, C_SPILL_RHO, kWG);
           }
@@ -2138,9 +2192,9 @@ __global__ void k_set_desc(RunDesc d, RunDesc* dd) {
 // ---------------------------------------------------------------------------
 // Host launches.
 // ---------------------------------------------------------------------------
-// Dynamic LDS of the density kernel: per staged hit a 12-byte record, its hit
-// index, a 16-bit tile id and four 16-bit quad-list entries, then the region's
-// tile offsets and quad-list offsets.
+// Dynamic LDS of the density kernel: per staged hit 16 bytes of record and
+// hit index, a 16-bit tile id and four 16-bit quad-list entries, then the
+// region's tile offsets and quad-list offsets.
 int lds_bytes_for(const Geom& g) { return lds_records_density(g.lds_cap) + 4 * (g.ts_ints + g.q_ints); }
 // Nearest-higher: per staged hit a float4 record, a 16-bit queue entry and its
 // region row (a byte), then the region's tile offsets.
