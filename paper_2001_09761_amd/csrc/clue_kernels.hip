@@ -862,7 +862,6 @@ struct Staged {
       return *reinterpret_cast<const float2*>(rec(j));
     }
   }
-  __device__ __forceinline__ float e(int j) const { return rec(j)[2]; }
   __device__ __forceinline__ const int* key_ptr(int j) const {
     if constexpr (kSplit) return reinterpret_cast<const int*>(base + 12 * cap) + j;
     else return reinterpret_cast<const int*>(base + 16 * j + 12);
