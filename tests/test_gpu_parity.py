@@ -401,3 +401,23 @@ def test_staged_dense_tiles_long_lower_bound_searches(tuning, batched):
     p = dict(ADV_P, n_layers=2)
     print(f"staged dense tiles: {x.size} hits, tuning {tuning}, batched {batched}", flush=True)
     assert_parity(gpu_run(ev, p, batched=batched, tuning=tuning), _ref(ev, p), where="staged dense tiles")
+
+
+@pytest.mark.parametrize("tuning", [dict(density_quads=2, lds_cap=2048, plain_lds_cap=2048, block_x=16, block_y=16),
+                                    dict(tile_size=2.5, lds_cap=2048, plain_lds_cap=2048, block_x=8, block_y=8)])
+@pytest.mark.parametrize("batched", [False, True])
+def test_staged_dense_tiles_per_query_merges(tuning, batched):
+    """The same dense staged tiles through the per-query merges instead of
+    quad lists: without quad lists at the default tile (12-byte records, the
+    two-tile instance) and at a 2.5 cm tile, where a window spans three tiles
+    (16-byte records, the three-tile instance). Tiles of more than 64 hits
+    take the full merge. Every output equals the oracle's."""
+    rng = np.random.default_rng(22)
+    x = np.concatenate([rng.uniform(4.1, 7.9, 600), rng.uniform(8.2, 11.9, 250), rng.uniform(0.0, 20.0, 200)])
+    y = np.concatenate([rng.uniform(4.1, 7.9, 600), rng.uniform(4.1, 7.9, 250), rng.uniform(0.0, 20.0, 200)])
+    order = rng.permutation(x.size)
+    ev = dict(x=x[order].astype(np.float32), y=y[order].astype(np.float32), layer=np.zeros(x.size, np.int32),
+              energy=rng.uniform(0.1, 1.0, x.size).astype(np.float32))
+    p = dict(ADV_P, n_layers=1)
+    print(f"per-query merges on dense tiles: tuning {tuning}, batched {batched}", flush=True)
+    assert_parity(gpu_run(ev, p, batched=batched, tuning=tuning), _ref(ev, p), where="per-query merges")
