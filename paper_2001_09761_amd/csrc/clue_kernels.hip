@@ -770,7 +770,7 @@ __device__ __forceinline__ Window query_window(const Geom& g, float w, float xi,
 // in ascending j. Tiles list their hits in ascending index; a query first marks
 // the passing hits of each window tile in a 64-bit mask, then merges only the
 // passing hits of the (at most MAXL x MAXL) sorted tile lists.
-// Staged records: (x, y, E), with the hit indices in an array beside them.
+// Staged records: (x, y, E) and the hit index, laid out per instance (Staged).
 // ---------------------------------------------------------------------------
 // exp(x) for x <= 0 as one fixed binary32 evaluation, after Cody and Waite's
 // range reduction: x = k ln2 + r with k = floor(x / ln2 + 1/2) and ln2 split
