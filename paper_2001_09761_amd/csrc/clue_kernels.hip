@@ -677,19 +677,6 @@ __device__ __forceinline__ void region_setup(const Geom& g, const Arena& a, Regi
   R.total = L.row_lo[R.rh];
 }
 
-// Region row containing LDS position p (row_lo is non-decreasing).
-__device__ __forceinline__ int region_row_of(const RegionLds& L, int rh, int p) {
-  int lo = 0, hi = rh - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (L.row_lo[mid] <= p)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  return lo;
-}
-
 // Core query q -> (region row, LDS position). `cr` is a core row at or
 // before q's, and is left at q's: a lane walking its queries in increasing
 // order keeps it between calls.
@@ -1642,18 +1629,23 @@ __device__ __forceinline__ bool nh_staged(const Geom& g, const Arena& a, const R
                           float4* rec, unsigned short* queue, unsigned char* prow, int* s_qn, int ev_first) {
   const int per_row = R.rw + 1;
   const int64_t ubase = (int64_t)R.unit * g.tpl;
-  // every global load of a lane is issued before its first LDS store; the
-  // region row of each staged position is kept for the winners' slots
+  // the region row of every staged position, 16 lanes per row (it gives the
+  // staging loads their slots and the winners theirs)
+  for (int k = threadIdx.x; k < 16 * R.rh; k += kWG) {
+    const int r = k >> 4;
+    const int end = L.row_lo[r + 1];
+    for (int p = L.row_lo[r] + (k & 15); p < end; p += 16) prow[p] = (unsigned char)r;
+  }
+  __syncthreads();
+  // every global load of a lane is issued before its first LDS store
   bool outside = false;  // a hit whose event-local index does not fit the packed word
   for (int base = 0; base < R.total; base += kStagePer * kWG) {
     float4 v[kStagePer];
-    int rw[kStagePer];
 #pragma unroll
     for (int k = 0; k < kStagePer; ++k) {
       const int p = base + (int)threadIdx.x + k * kWG;
       if (p < R.total) {
-        rw[k] = region_row_of(L, R.rh, p);
-        const int s = slot_of(L, rw[k], p);
+        const int s = slot_of(L, prow[p], p);
         v[k] = make_float4(a.xs[s], a.ys[s], a.rho[s], __int_as_float(a.hs[s]));
       }
     }
@@ -1664,7 +1656,6 @@ __device__ __forceinline__ bool nh_staged(const Geom& g, const Arena& a, const R
         outside |= (unsigned)(__float_as_int(v[k].w) - ev_first) >= (unsigned)kPackedEventMax;
         rec[p] = make_float4(v[k].x, v[k].y, __uint_as_float(nh_pack(__float_as_int(v[k].w), ev_first, p)),
                              __uint_as_float(ord_f32(v[k].z)));
-        prow[p] = (unsigned char)rw[k];
       }
     }
   }
