@@ -685,10 +685,6 @@ __device__ __forceinline__ void core_query(const RegionLds& L, const Region& R, 
   row = R.cy0 + cr;
   p = L.ts[row * (R.rw + 1) + R.cx0] + (q - L.core_lo[cr]);
 }
-__device__ __forceinline__ void core_query(const RegionLds& L, const Region& R, int q, int& row, int& p) {
-  int cr = 0;
-  core_query(L, R, q, cr, row, p);
-}
 
 __device__ __forceinline__ int slot_of(const RegionLds& L, int row, int p) { return L.row_gs[row] + (p - L.row_lo[row]); }
 
@@ -1668,10 +1664,10 @@ __device__ __forceinline__ bool nh_staged(const Geom& g, const Arena& a, const R
   // phase 1: radius r1; only hits strictly within r1 can settle a query here
   int cr = 0;
   for (int q = threadIdx.x; q < nq; q += kWG) {
+    int row, p;
+    core_query(L, R, q, cr, row, p);
     bool done = false;
     if (g.nh_phase1) {
-      int row, p;
-      core_query(L, R, q, cr, row, p);
       const float4 me = rec[p];
       const unsigned ordi = __float_as_uint(me.w), zi = __float_as_uint(me.z);
       const Window W = query_window(g, g.win_r1, me.x, me.y);
@@ -1688,7 +1684,7 @@ __device__ __forceinline__ bool nh_staged(const Geom& g, const Arena& a, const R
         }
       }
     }
-    if (!done) queue[atomicAdd(s_qn, 1)] = (unsigned short)q;
+    if (!done) queue[atomicAdd(s_qn, 1)] = (unsigned short)p;  // its LDS position
   }
   __syncthreads();
   // phase 2: full d_m window, tpq lanes per query
@@ -1704,9 +1700,8 @@ __device__ __forceinline__ bool nh_staged(const Geom& g, const Arena& a, const R
     int slot = 0;
     unsigned hi = 0, ordi = 0;
     if (active) {
-      int row, p;
-      core_query(L, R, queue[qi], row, p);
-      slot = slot_of(L, row, p);
+      const int p = queue[qi];
+      slot = slot_of(L, prow[p], p);
       const float4 me = rec[p];
       ordi = __float_as_uint(me.w);
       const unsigned zi = __float_as_uint(me.z);
