@@ -21,8 +21,8 @@ constexpr int kMaxLdsCap = 2048;
 // hit index, 16-bit tile id, four 16-bit quad entries), rounded up to 16.
 __host__ __device__ constexpr int lds_records_density(int lds_cap) { return (lds_cap * (12 + 4 + 2 + 8) + 15) & ~15; }
 // ... and of the nearest-higher kernel's (float4 record, 16-bit queue entry,
-// 8-bit region row).
-__host__ __device__ constexpr int lds_records_nh(int lds_cap) { return (lds_cap * (16 + 2 + 1) + 15) & ~15; }
+// 16-bit core-query position, 8-bit region row).
+__host__ __device__ constexpr int lds_records_nh(int lds_cap) { return (lds_cap * (16 + 2 + 2 + 1) + 15) & ~15; }
 static_assert(kMaxLdsCap <= 65536, "nearest-higher queue entries are 16-bit");
 constexpr int kStagePer = 4;       // staged hits per lane per round (loads in flight)
 constexpr int kPlaceU = 4;         // hits per lane per step of the streaming grid-build and list kernels

@@ -1622,15 +1622,23 @@ __device__ __forceinline__ void nh_global_scan(const Geom& g, const Arena& a, in
 // global memory.
 template <bool STRICT>
 __device__ __forceinline__ bool nh_staged(const Geom& g, const Arena& a, const RunDesc& d, const Region& R, const RegionLds& L,
-                          float4* rec, unsigned short* queue, unsigned char* prow, int* s_qn, int ev_first) {
+                          float4* rec, unsigned short* queue, unsigned char* prow, unsigned short* coreq, int* s_qn,
+                          int ev_first) {
   const int per_row = R.rw + 1;
   const int64_t ubase = (int64_t)R.unit * g.tpl;
-  // the region row of every staged position, 16 lanes per row (it gives the
-  // staging loads their slots and the winners theirs)
+  // the region row of every staged position (it gives the staging loads
+  // their slots and the winners theirs), and the LDS position of every core
+  // query, 16 lanes per row
   for (int k = threadIdx.x; k < 16 * R.rh; k += kWG) {
     const int r = k >> 4;
     const int end = L.row_lo[r + 1];
     for (int p = L.row_lo[r] + (k & 15); p < end; p += 16) prow[p] = (unsigned char)r;
+    const int cr = r - R.cy0;
+    if (cr >= 0 && cr < R.ch) {
+      const int p0 = L.ts[r * per_row + R.cx0];
+      const int q1 = L.core_lo[cr + 1];
+      for (int q = L.core_lo[cr] + (k & 15); q < q1; q += 16) coreq[q] = (unsigned short)(p0 + q - L.core_lo[cr]);
+    }
   }
   __syncthreads();
   // every global load of a lane is issued before its first LDS store
@@ -1662,10 +1670,9 @@ __device__ __forceinline__ bool nh_staged(const Geom& g, const Arena& a, const R
   if (__syncthreads_or(outside)) return false;
   const int nq = L.core_lo[R.ch];
   // phase 1: radius r1; only hits strictly within r1 can settle a query here
-  int cr = 0;
   for (int q = threadIdx.x; q < nq; q += kWG) {
-    int row, p;
-    core_query(L, R, q, cr, row, p);
+    const int p = coreq[q];
+    const int row = prow[p];
     bool done = false;
     if (g.nh_phase1) {
       const float4 me = rec[p];
@@ -1763,7 +1770,8 @@ __device__ __forceinline__ void nh_global_region(const Geom& g, const Arena& a, 
 
 template <bool STRICT>
 __device__ __forceinline__ void nh_item(const Geom& g, const Arena& a, const RunDesc& d, int item, RegionLds& L,
-                                        float4* rec, unsigned short* queue, unsigned char* prow, int* s_qn) {
+                                        float4* rec, unsigned short* queue, unsigned char* prow, unsigned short* coreq,
+                                        int* s_qn) {
   int unit, tx0, ty0, tx1, ty1;
   item_block(g, item, unit, tx0, ty0, tx1, ty1);
   Region R;
@@ -1778,7 +1786,7 @@ __device__ __forceinline__ void nh_item(const Geom& g, const Arena& a, const Run
     return;
   }
   if (R.total <= g.lds_cap) {
-    if (!nh_staged<STRICT>(g, a, d, R, L, rec, queue, prow, s_qn, ev_first)) nh_global_region<STRICT>(g, a, d, R, L, ev_first);
+    if (!nh_staged<STRICT>(g, a, d, R, L, rec, queue, prow, coreq, s_qn, ev_first)) nh_global_region<STRICT>(g, a, d, R, L, ev_first);
     return;
   }
   // too dense: the four quarter blocks, then single tiles
@@ -1789,7 +1797,7 @@ __device__ __forceinline__ void nh_item(const Geom& g, const Arena& a, const Run
       make_region(g, unit, sx, sy, ex, ey, R);
       region_setup(g, a, R, L);
       if (L.core_lo[R.ch] == 0) continue;
-      if (R.total <= g.lds_cap && nh_staged<STRICT>(g, a, d, R, L, rec, queue, prow, s_qn, ev_first)) continue;
+      if (R.total <= g.lds_cap && nh_staged<STRICT>(g, a, d, R, L, rec, queue, prow, coreq, s_qn, ev_first)) continue;
       if (R.total <= g.lds_cap) {
         nh_global_region<STRICT>(g, a, d, R, L, ev_first);
         continue;
@@ -1801,7 +1809,7 @@ __device__ __forceinline__ void nh_item(const Geom& g, const Arena& a, const Run
           if (L.core_lo[R.ch] == 0) continue;
           if (R.total > g.lds_cap)
             spill_region(g, a, R, C_SPILL_NH, kWG / g.tpq);
-          else if (!nh_staged<STRICT>(g, a, d, R, L, rec, queue, prow, s_qn, ev_first))
+          else if (!nh_staged<STRICT>(g, a, d, R, L, rec, queue, prow, coreq, s_qn, ev_first))
             nh_global_region<STRICT>(g, a, d, R, L, ev_first);
         }
     }
@@ -1849,12 +1857,13 @@ __global__ __launch_bounds__(kWG, 8) void k_nearest_higher(DescArg<G> dg, Geom g
   __shared__ int s_item;
   float4* rec = reinterpret_cast<float4*>(smem);
   unsigned short* queue = reinterpret_cast<unsigned short*>(rec + g.lds_cap);
-  unsigned char* prow = reinterpret_cast<unsigned char*>(queue + g.lds_cap);
+  unsigned short* coreq = queue + g.lds_cap;
+  unsigned char* prow = reinterpret_cast<unsigned char*>(coreq + g.lds_cap);
   RegionLds L = region_lds(s_rows, reinterpret_cast<int*>(smem + lds_records_nh(g.lds_cap)), nullptr);
   const int n_items = d.n_events * g.L * g.bpu;
   ItemSched st{0, G ? xcc_id() : 0};
   for (int item; (item = next_item<G>(st, n_items, &a.counters[C_QUEUE_NH], &s_item)) >= 0;)
-    nh_item<STRICT>(g, a, d, item, L, rec, queue, prow, &s_qn);
+    nh_item<STRICT>(g, a, d, item, L, rec, queue, prow, coreq, &s_qn);
 }
 
 // ---------------------------------------------------------------------------
@@ -2181,8 +2190,9 @@ __global__ void k_set_desc(RunDesc d, RunDesc* dd) {
 // hit index, a 16-bit tile id and four 16-bit quad-list entries, then the
 // region's tile offsets and quad-list offsets.
 int lds_bytes_for(const Geom& g) { return lds_records_density(g.lds_cap) + 4 * (g.ts_ints + g.q_ints); }
-// Nearest-higher: per staged hit a float4 record, a 16-bit queue entry and its
-// region row (a byte), then the region's tile offsets.
+// Nearest-higher: per staged hit a float4 record, a 16-bit queue entry, a
+// 16-bit core-query position and its region row (a byte), then the region's
+// tile offsets.
 int lds_bytes_nh(const Geom& g) { return lds_records_nh(g.lds_cap) + 4 * g.ts_ints; }
 
 static inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
