@@ -1576,6 +1576,20 @@ __device__ __forceinline__ void decide_and_store(const Geom& g, const Arena& a, 
   }
 }
 
+// One staged record r for query i. The eligibility test comes first, and the
+// scheduling barrier keeps the distance arithmetic after it: the record's rho
+// word is then dead when d2 is formed, so d2 takes its register and
+// (index word, d2) is already the register pair of the candidate key.
+template <bool STRICT>
+__device__ __forceinline__ void nh_consider_rec(NhBest& b, float4 r, float xi, float yi, unsigned ordi, unsigned hi) {
+  const unsigned ordj = __float_as_uint(r.w), hj = __float_as_uint(r.z);
+  const bool higher = STRICT ? ordj > ordi : key64(ordj, hj) > key64(ordi, hi);
+  __builtin_amdgcn_sched_barrier(0);
+  const unsigned long long ck = key64(__float_as_uint(dist2(xi, yi, r.x, r.y)), hj);
+  const bool take = higher & (ck < b.k);
+  b.k = take ? ck : b.k;
+}
+
 // Scans window tiles [tx0..tx1] x [ty0..ty1] (region coordinates) of the
 // staged records (x, y, index, ord(rho)) with lanes sub, sub + step, ...
 template <bool STRICT>
@@ -1590,18 +1604,12 @@ __device__ __forceinline__ void nh_scan_staged(const float4* __restrict__ rec, c
     // four independent LDS loads in flight per step
     for (; c < c4; c += 4 * step) {
       const float4 r0 = rec[c], r1 = rec[c + step], r2 = rec[c + 2 * step], r3 = rec[c + 3 * step];
-      nh_consider<STRICT, false>(b, dist2(xi, yi, r0.x, r0.y), __float_as_uint(r0.w), __float_as_uint(r0.z), c, ordi, hi);
-      nh_consider<STRICT, false>(b, dist2(xi, yi, r1.x, r1.y), __float_as_uint(r1.w), __float_as_uint(r1.z), c + step,
-                          ordi, hi);
-      nh_consider<STRICT, false>(b, dist2(xi, yi, r2.x, r2.y), __float_as_uint(r2.w), __float_as_uint(r2.z),
-                          c + 2 * step, ordi, hi);
-      nh_consider<STRICT, false>(b, dist2(xi, yi, r3.x, r3.y), __float_as_uint(r3.w), __float_as_uint(r3.z),
-                          c + 3 * step, ordi, hi);
+      nh_consider_rec<STRICT>(b, r0, xi, yi, ordi, hi);
+      nh_consider_rec<STRICT>(b, r1, xi, yi, ordi, hi);
+      nh_consider_rec<STRICT>(b, r2, xi, yi, ordi, hi);
+      nh_consider_rec<STRICT>(b, r3, xi, yi, ordi, hi);
     }
-    for (; c < q1; c += step) {
-      const float4 r = rec[c];
-      nh_consider<STRICT, false>(b, dist2(xi, yi, r.x, r.y), __float_as_uint(r.w), __float_as_uint(r.z), c, ordi, hi);
-    }
+    for (; c < q1; c += step) nh_consider_rec<STRICT>(b, rec[c], xi, yi, ordi, hi);
   }
 }
 
