@@ -17,9 +17,16 @@ constexpr int kMaxRegionTiles = 640;   // staged region tiles, rows x (cols + 1)
 constexpr int kMaxRegionRows = 64;
 constexpr int kDefaultLdsCap = 960;    // staged hits per workgroup (fast path)
 constexpr int kMaxLdsCap = 2048;
-// Bytes of the density kernel's per-hit LDS arrays (16 bytes of record and
-// hit index, 16-bit tile id, four 16-bit quad entries), rounded up to 16.
-__host__ __device__ constexpr int lds_records_density(int lds_cap) { return (lds_cap * (12 + 4 + 2 + 8) + 15) & ~15; }
+// The density kernel's LDS arrays: per staged hit 16 bytes of record and hit
+// index, then a 16-bit tile id per hit, then four 16-bit quad-list entries per
+// hit (from an 8-byte boundary), then one 16-byte sentinel record, rounded up
+// to 16 bytes.
+__host__ __device__ constexpr int density_qidx_offset(int lds_cap) { return (lds_cap * (16 + 2) + 7) & ~7; }
+__host__ __device__ constexpr int density_sentinel_offset(int lds_cap) {
+  return (density_qidx_offset(lds_cap) + lds_cap * 8 + 15) & ~15;
+}
+__host__ __device__ constexpr int lds_records_density(int lds_cap) { return density_sentinel_offset(lds_cap) + 16; }
+static_assert(density_sentinel_offset(2048) + 16 <= 65536, "quad-list entries are 16-bit LDS byte offsets");
 // ... and of the nearest-higher kernel's (float4 record, 16-bit queue entry,
 // 16-bit core-query position, 8-bit region row).
 __host__ __device__ constexpr int lds_records_nh(int lds_cap) { return (lds_cap * (16 + 2 + 2 + 1) + 15) & ~15; }

@@ -1096,7 +1096,7 @@ static_assert(kMaxRegionRows <= 64 && kMaxRegionTiles <= 1024, "a staged tile id
 template <int MAXL, int K>
 __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, const Region& R, RegionLds& L,
                                                const Staged<MAXL>& S, unsigned short* stile, unsigned short* qidx,
-                                               bool keep) {
+                                               unsigned short sent, bool keep) {
   const int per_row = R.rw + 1;
   const int64_t ubase = (int64_t)R.unit * g.tpl;
   const int ntl = R.rh * per_row;
@@ -1139,7 +1139,10 @@ __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, co
   bool use_quads = MAXL == 2 && g.density_quads && nquad < g.q_ints;
   if (use_quads) {
     if (threadIdx.x < 64) {
-      // quad sizes -> offsets, 64 quads per wave step
+      // quad sizes -> offsets, 64 quads per wave step. Each list is padded
+      // with the sentinel to a multiple of four entries, so the queries read
+      // their lists four entries at a time with no remainder loop (pads past
+      // the array are not written: the quads are then not used).
       int run = 0;
       for (int q0 = 0; q0 < nquad; q0 += 64) {
         const int q = q0 + (int)threadIdx.x;
@@ -1149,8 +1152,13 @@ __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, co
           const int bx1 = min(ax + 1, R.rw - 1), by1 = min(ay + 1, R.rh - 1);
           for (int ty = ay; ty <= by1; ++ty) len += L.ts[ty * per_row + bx1 + 1] - L.ts[ty * per_row + ax];
         }
-        const int incl = wave_incl_scan(len, threadIdx.x);
-        if (q < nquad) L.qoff[q] = run + incl - len;
+        const int plen = (len + 3) & ~3;
+        const int incl = wave_incl_scan(plen, threadIdx.x);
+        if (q < nquad) {
+          const int o = run + incl - plen;
+          L.qoff[q] = o;
+          for (int i = o + len; i < o + plen && i < 4 * g.lds_cap; ++i) qidx[i] = sent;
+        }
         run += __builtin_amdgcn_readlane(incl, 63);
       }
       if (threadIdx.x == 0) {
@@ -1176,7 +1184,7 @@ __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, co
         end[k] = dup ? 0 : L.ts[t + 1];
         key[k] = cur[k] < end[k] ? S.key(cur[k]) : INT_MAX;
       }
-      const int out = L.qoff[q], n = L.qoff[q + 1] - out;
+      const int out = L.qoff[q], n = (end[0] - cur[0]) + (end[1] - cur[1]) + (end[2] - cur[2]) + (end[3] - cur[3]);
       for (int i = 0; i < n; ++i) {
         const int m = min(min(key[0], key[1]), min(key[2], key[3]));
         const bool s0 = key[0] == m, s1 = !s0 && key[1] == m, s2 = !s0 && !s1 && key[2] == m;
@@ -1327,9 +1335,9 @@ __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, co
       const int qq = (ty0 - qy0) * qw + (tx0 - qx0);
       const unsigned short* qp = qidx + L.qoff[qq];
       const unsigned short* const qe = qidx + L.qoff[qq + 1];
-      const unsigned short* const qe4 = qe - 3;
-      // loads batched four at a time; additions stay in ascending index order
-      for (; qp < qe4; qp += 4) {
+      // four entries at a time (the lists are padded to a multiple of four);
+      // additions stay in ascending index order
+      for (; qp < qe; qp += 4) {
         const int i0 = qp[0], i1 = qp[1], i2 = qp[2], i3 = qp[3];
         const Rec3 r0 = S.at(i0), r1 = S.at(i1), r2 = S.at(i2), r3 = S.at(i3);
         const float d0 = dist2(xi, yi, r0.x, r0.y), d1 = dist2(xi, yi, r1.x, r1.y);
@@ -1342,12 +1350,6 @@ __device__ __forceinline__ void density_staged(const Geom& g, const Arena& a, co
         rho = d2 < g.dc2 ? a2 : rho;
         const float a3 = __fadd_rn(rho, kernel_term<K>(d3, g.ka, r3.e));
         rho = d3 < g.dc2 ? a3 : rho;
-      }
-      for (; qp < qe; ++qp) {
-        const Rec3 r = S.at(*qp);
-        const float d = dist2(xi, yi, r.x, r.y);
-        const float a = __fadd_rn(rho, kernel_term<K>(d, g.ka, r.e));
-        rho = d < g.dc2 ? a : rho;
       }
     } else if (ok) {
       int lo[MAXL * MAXL], hi[MAXL * MAXL];
@@ -1430,7 +1432,12 @@ __global__ __launch_bounds__(kWG, density_min_waves(MAXL, K)) void k_density(Des
   __shared__ int s_item;
   const Staged<MAXL> S{smem, g.lds_cap};
   unsigned short* stile = reinterpret_cast<unsigned short*>(smem + 16 * g.lds_cap);  // both layouts: 16 B per hit
-  unsigned short* qidx = stile + g.lds_cap;
+  unsigned short* qidx = reinterpret_cast<unsigned short*>(smem + density_qidx_offset(g.lds_cap));
+  // the record every quad list is padded with, to a multiple of four entries:
+  // x = +inf puts it at an infinite squared distance from every query
+  const unsigned short sent = (unsigned short)density_sentinel_offset(g.lds_cap);
+  if (threadIdx.x == 0)
+    *reinterpret_cast<float4*>(smem + sent) = make_float4(__int_as_float(0x7f800000), 0.0f, 0.0f, 0.0f);
   int* meta = reinterpret_cast<int*>(smem + lds_records_density(g.lds_cap));
   RegionLds L = region_lds(s_rows, meta, meta + g.ts_ints);
   const int n_items = d.n_events * g.L * g.bpu;
@@ -1444,7 +1451,7 @@ __global__ __launch_bounds__(kWG, density_min_waves(MAXL, K)) void k_density(Des
     region_setup(g, a, R, L);
     if (L.core_lo[R.ch] == 0) continue;
     if (R.total <= g.lds_cap) {
-      density_staged<MAXL, K>(g, a, R, L, S, stile, qidx, keep);
+      density_staged<MAXL, K>(g, a, R, L, S, stile, qidx, sent, keep);
       continue;
     }
     // too dense: the four quarter blocks, then single tiles
@@ -1456,7 +1463,7 @@ __global__ __launch_bounds__(kWG, density_min_waves(MAXL, K)) void k_density(Des
         region_setup(g, a, R, L);
         if (L.core_lo[R.ch] == 0) continue;
         if (R.total <= g.lds_cap) {
-          density_staged<MAXL, K>(g, a, R, L, S, stile, qidx, keep);
+          density_staged<MAXL, K>(g, a, R, L, S, stile, qidx, sent, keep);
           continue;
         }
         for (int ty = sy; ty <= ey; ++ty)
@@ -1465,7 +1472,7 @@ __global__ __launch_bounds__(kWG, density_min_waves(MAXL, K)) void k_density(Des
             region_setup(g, a, R, L);
             if (L.core_lo[R.ch] == 0) continue;
             if (R.total <= g.lds_cap)
-              density_staged<MAXL, K>(g, a, R, L, S, stile, qidx, keep);
+              density_staged<MAXL, K>(g, a, R, L, S, stile, qidx, sent, keep);
             else
               spill_region(g, a, R, C_SPILL_RHO, kWG);
           }
