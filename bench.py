@@ -45,12 +45,14 @@ ALG_BYTES = {
 PIPELINE_ALG_BYTES = 85.0
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "density_1M-hit-x32_traffic.json")
 PROFILE_ISSUE = os.path.join(ROOT, "profiles", "density_1M-hit-x32_valu_issue.json")
-# Non-packed FP32 issue ceiling: the published 157.3 TFLOP/s FP32 vector peak is
+# Non-packed FP32 issue rate: the published 157.3 TFLOP/s FP32 vector peak is
 # 256 CUs x 2.4 GHz x 256 flop per CU-cycle with packed two-wide FMAs, i.e. one
-# wave64 instruction per CU-cycle without packing (the kernels are built without it).
+# wave64 instruction per CU-cycle without packing (the kernels are built without
+# it). SQ_INSTS_VALU also counts integer, compare and select instructions, and a
+# kernel whose mix holds many of them measures above this rate.
 CU_COUNT = 256
 CLOCK_GHZ = 2.4
-VALU_ISSUE_CEILING = 1.0  # wave64 VALU instructions per CU-cycle
+VALU_FP32_ISSUE_RATE = 1.0  # wave64 VALU instructions per CU-cycle
 
 
 def code_sha(sources) -> str:
@@ -435,17 +437,17 @@ def main():
                                     "source": os.path.relpath(PROFILE_TRAFFIC, ROOT)}
     except (OSError, ValueError, KeyError):
         traffic = None
-    # how close the kernel runs to its issue ceiling: SQ_INSTS_VALU per launch
-    # from the committed profile of the same kernel source, over this run's
-    # launch duration
+    # the kernel's VALU issue rate: SQ_INSTS_VALU per launch from the committed
+    # profile of the same kernel source, over this run's launch duration, and
+    # as a multiple of the non-packed FP32 rate
     valu_issue = None
     try:
         iss = json.load(open(PROFILE_ISSUE))
         if iss.get("kernel_source_sha") == kernel_source_sha() and iss.get("stage") == dom \
                 and int(iss.get("hits_per_launch", -1)) == n:
             per_cycle = iss["sq_insts_valu_per_launch"] / (CU_COUNT * dom_ms * 1e-3 * CLOCK_GHZ * 1e9)
-            valu_issue = {"valu_insts_per_cu_cycle": round(per_cycle, 3), "ceiling": VALU_ISSUE_CEILING,
-                          "frac": round(per_cycle / VALU_ISSUE_CEILING, 3),
+            valu_issue = {"valu_insts_per_cu_cycle": round(per_cycle, 3), "fp32_issue_rate": VALU_FP32_ISSUE_RATE,
+                          "vs_fp32_issue_rate": round(per_cycle / VALU_FP32_ISSUE_RATE, 3),
                           "lane_slots_per_hit": round(iss["sq_insts_valu_per_launch"] * 64 / n, 1),
                           "source": os.path.relpath(PROFILE_ISSUE, ROOT)}
     except (OSError, ValueError, KeyError):
@@ -620,7 +622,7 @@ def issue_summary(d, stage, n_events, out_path=None):
     hits = 10000 * 100 * n_events
     out = {"stage": stage, "kernel_match": kname, "kernel_source_sha": kernel_source_sha(),
            "hits_per_launch": hits, "sq_insts_valu_per_launch": valu, "dispatches": nv,
-           "avg_duration_ns": ns, "valu_insts_per_cu_cycle": per_cycle, "ceiling": VALU_ISSUE_CEILING,
+           "avg_duration_ns": ns, "valu_insts_per_cu_cycle": per_cycle, "fp32_issue_rate": VALU_FP32_ISSUE_RATE,
            "commands": {
                "sq": "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc SQ_INSTS_VALU SQ_INSTS_LDS "
                      "SQ_LDS_BANK_CONFLICT SQ_ACTIVE_INST_LDS SQ_WAIT_INST_LDS SQ_BUSY_CYCLES SQ_WAVE_CYCLES "
