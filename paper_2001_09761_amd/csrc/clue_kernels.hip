@@ -1517,17 +1517,16 @@ __device__ __forceinline__ NhBest nh_start(float thr) { return NhBest{key64(__fl
 
 // One candidate j for query i: eligible when j is higher (ord/index keys);
 // keeps the lexicographic minimum of (d2, index), which starts at
-// nh_start(thr). d2 >= 0, so its bit pattern orders like its value.
-// TRACK = false leaves b.p alone: the staged scan packs the LDS position into
-// the index word instead (see nh_pack).
-template <bool STRICT, bool TRACK = true>
+// nh_start(thr), and the candidate's position pq. d2 >= 0, so its bit
+// pattern orders like its value.
+template <bool STRICT>
 __device__ __forceinline__ void nh_consider(NhBest& b, float d2, unsigned ordj, unsigned hj, int pq, unsigned ordi,
                                             unsigned hi) {
   const bool higher = STRICT ? ordj > ordi : key64(ordj, hj) > key64(ordi, hi);
   const unsigned long long ck = key64(__float_as_uint(d2), hj);
   const bool take = higher & (ck < b.k);  // branch-free select
   b.k = take ? ck : b.k;
-  if (TRACK) b.p = take ? pq : b.p;
+  b.p = take ? pq : b.p;
 }
 
 // Staged records carry, in place of the caller index, the word
@@ -1583,10 +1582,11 @@ __device__ __forceinline__ void decide_and_store(const Geom& g, const Arena& a, 
   }
 }
 
-// One staged record r for query i. The eligibility test comes first, and the
-// scheduling barrier keeps the distance arithmetic after it: the record's rho
-// word is then dead when d2 is formed, so d2 takes its register and
-// (index word, d2) is already the register pair of the candidate key.
+// One staged record r for query i, as nh_consider but tracking no position:
+// the record's index word carries it (nh_pack). The eligibility test comes
+// first, and the scheduling barrier keeps the distance arithmetic after it:
+// the record's rho word is then dead when d2 is formed, so d2 takes its
+// register and (index word, d2) is already the register pair of the key.
 template <bool STRICT>
 __device__ __forceinline__ void nh_consider_rec(NhBest& b, float4 r, float xi, float yi, unsigned ordi, unsigned hi) {
   const unsigned ordj = __float_as_uint(r.w), hj = __float_as_uint(r.z);
