@@ -421,3 +421,43 @@ def test_staged_dense_tiles_per_query_merges(tuning, batched):
     p = dict(ADV_P, n_layers=1)
     print(f"per-query merges on dense tiles: tuning {tuning}, batched {batched}", flush=True)
     assert_parity(gpu_run(ev, p, batched=batched, tuning=tuning), _ref(ev, p), where="per-query merges")
+
+
+
+@pytest.mark.parametrize("tuning", [dict(tile_size=4.5, block_x=4, block_y=4, lds_cap=2048, plain_lds_cap=2048),
+                                    dict(tile_size=4.5, block_x=8, block_y=8, lds_cap=64, plain_lds_cap=64),
+                                    dict(tile_size=4.5, block_x=8, block_y=8, lds_cap=96, plain_lds_cap=96),
+                                    dict(tile_size=4.5, block_x=4, block_y=4, density_quads=2, lds_cap=256,
+                                         plain_lds_cap=256)])
+@pytest.mark.parametrize("kernel", ["flat", "gaussian"])
+@pytest.mark.parametrize("batched", [False, True])
+def test_quad_lists_of_every_length_residue(tuning, kernel, batched):
+    """Quad lists of every length modulo four, which the density queries read
+    padded to a multiple of four entries with a record at infinite distance.
+    On a 24 x 24 grid of 4.5 cm tiles, two layers hold 0..7 hits per tile, so
+    the lists take every residue. The third layer is a checkerboard of single
+    hits. With 8 x 8-tile blocks, an interior block stages 50 of them and its
+    81 quads hold two each: 324 padded entries, which overflow the entry
+    array at a 64-hit cap (the per-query merge runs instead) and fit at a
+    96-hit cap; a corner block's 64 quads fill the 256 entries of the 64-hit
+    cap exactly. Every output equals the oracle's, also with the Gaussian
+    kernel, whose term is evaluated (and discarded) for the padding record."""
+    rng = np.random.default_rng(23)
+    t, nt = 4.5, 24
+    xs, ys, ls = [], [], []
+    for layer in range(3):
+        for ty in range(nt):
+            for tx in range(nt):
+                k = (tx + nt * ty + 3 * layer) % 8 if layer < 2 else (tx + ty + 1) % 2
+                xs.append(rng.uniform(tx * t + 0.01, (tx + 1) * t - 0.01, k))
+                ys.append(rng.uniform(ty * t + 0.01, (ty + 1) * t - 0.01, k))
+                ls.append(np.full(k, layer, np.int32))
+    x, y, layer = np.concatenate(xs), np.concatenate(ys), np.concatenate(ls)
+    order = rng.permutation(x.size)
+    ev = dict(x=x[order].astype(np.float32), y=y[order].astype(np.float32), layer=layer[order],
+              energy=rng.uniform(0.1, 1.0, x.size).astype(np.float32))
+    p = dict(ADV_P, bounds=(0, 0, nt * t, nt * t), n_layers=3)
+    if kernel != "flat":
+        p.update(kernel=kernel, kernel_scale=1.0)
+    print(f"quad lists of every residue: {x.size} hits, {kernel}, tuning {tuning}, batched {batched}", flush=True)
+    assert_parity(gpu_run(ev, p, batched=batched, tuning=tuning), _ref(ev, p), where="quad list residues")
