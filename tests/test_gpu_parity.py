@@ -461,3 +461,35 @@ def test_quad_lists_of_every_length_residue(tuning, kernel, batched):
         p.update(kernel=kernel, kernel_scale=1.0)
     print(f"quad lists of every residue: {x.size} hits, {kernel}, tuning {tuning}, batched {batched}", flush=True)
     assert_parity(gpu_run(ev, p, batched=batched, tuning=tuning), _ref(ev, p), where="quad list residues")
+
+
+@pytest.mark.parametrize("tuning", [dict(tile_size=4.5, block_x=4, block_y=4, lds_cap=2048, plain_lds_cap=2048),
+                                    dict(tile_size=4.5, block_x=3, block_y=5, lds_cap=256, plain_lds_cap=256,
+                                         threads_per_query=8),
+                                    dict(tile_size=4.5, block_x=5, block_y=3, lds_cap=2048, plain_lds_cap=2048,
+                                         threads_per_query=1, nh_first_radius=0.0)])
+@pytest.mark.parametrize("batched", [False, True])
+def test_nh_core_positions_with_empty_rows(tuning, batched):
+    """Nearest-higher reads each core query's staged position from an array
+    filled per region row. Every third tile row is empty, the others hold
+    0..6 hits per tile, so cores have empty rows, rows of one tile's hits and
+    ragged rows, and interior blocks start their core past the region's first
+    column; with phase 1 off every query goes through the phase-2 queue.
+    Every output equals the oracle's."""
+    rng = np.random.default_rng(24)
+    t, nt = 4.5, 24
+    xs, ys, ls = [], [], []
+    for layer in range(2):
+        for ty in range(nt):
+            for tx in range(nt):
+                k = 0 if (ty + layer) % 3 == 1 else (3 * tx + ty + layer) % 7
+                xs.append(rng.uniform(tx * t + 0.01, (tx + 1) * t - 0.01, k))
+                ys.append(rng.uniform(ty * t + 0.01, (ty + 1) * t - 0.01, k))
+                ls.append(np.full(k, layer, np.int32))
+    x, y, layer = np.concatenate(xs), np.concatenate(ys), np.concatenate(ls)
+    order = rng.permutation(x.size)
+    ev = dict(x=x[order].astype(np.float32), y=y[order].astype(np.float32), layer=layer[order],
+              energy=rng.uniform(0.1, 1.0, x.size).astype(np.float32))
+    p = dict(ADV_P, bounds=(0, 0, nt * t, nt * t), n_layers=2)
+    print(f"nh core positions: {x.size} hits, tuning {tuning}, batched {batched}", flush=True)
+    assert_parity(gpu_run(ev, p, batched=batched, tuning=tuning), _ref(ev, p), where="nh core positions")
